@@ -1,0 +1,357 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself.
+
+* Philox4x32-10 integer stream: two independent open-source library
+  implementations (PyTorch ATen's header-only engine and rocRAND's engine),
+  run on the host.
+* FP32 Box-Muller: exhaustively over all 2^23 uniforms against FP64 libm
+  log / cos / sin, plus distribution statistics of a large sample.
+* Product: special cases with exact answers (identity, selection matrices,
+  zero, power-of-two scaling, zero padding of the offset), numpy's FP64
+  matmul as a library routine, exactly rounded sums on tiny inputs, and the
+  contraction-split identity of Alg. 1.
+* Storage formats: torch's CPU casts to bfloat16 / float8_e4m3fn.
+"""
+import math
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+from sketch_inputs import normal_matrix, selection_matrix
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+# --------------------------------------------------------------------------
+# Philox integer stream
+# --------------------------------------------------------------------------
+def _counter_cases():
+    rng = np.random.default_rng(12345)
+    cases = []
+    seeds = [0, 1, 2, 0xFFFFFFFF, 1 << 32, (1 << 63) + 5, 0xFFFFFFFFFFFFFFFF]
+    qs = [0, 1, 2, 3, 0xFFFFFFFF, 1 << 32, (1 << 40) + 7, (1 << 62) - 1]
+    cs = [0, 1, 5, 255, 1 << 31, 0xFFFFFFFF]
+    for s in seeds:
+        for q in qs:
+            for c in cs:
+                cases.append((s, q, c, 0))
+    for _ in range(2000):
+        cases.append((int(rng.integers(0, 1 << 63)), int(rng.integers(0, 1 << 62)),
+                      int(rng.integers(0, 1 << 32)), int(rng.integers(0, 2))))
+    return cases
+
+
+def _run_pin(exe, cases):
+    text = "".join(f"{s} {q} {c} {st}\n" for s, q, c, st in cases)
+    out = subprocess.run([exe], input=text, capture_output=True, text=True, check=True).stdout
+    return np.array([[int(w) for w in line.split()] for line in out.strip().splitlines()],
+                    dtype=np.uint64).astype(np.uint32)
+
+
+def _oracle_words(cases):
+    ctr = np.array([[q & 0xFFFFFFFF, q >> 32, c, st] for s, q, c, st in cases], dtype=np.uint64)
+    out = []
+    for (s, _, _, _), row in zip(cases, ctr.astype(np.uint32)):
+        out.append(oracle.philox4x32_10(row[None, :], [s & 0xFFFFFFFF, s >> 32])[0])
+    return np.array(out, dtype=np.uint32)
+
+
+@pytest.fixture(scope="module")
+def pin_exes(tmp_path_factory):
+    d = tmp_path_factory.mktemp("pins")
+    exes = {}
+    import torch.utils.cpp_extension as ce
+
+    inc = [f"-I{p}" for p in ce.include_paths()]
+    aten = str(d / "pin_aten")
+    subprocess.run(["g++", "-O1", "-std=c++17", *inc, os.path.join(HERE, "pins", "philox_aten.cpp"),
+                    "-o", aten], check=True)
+    exes["aten"] = aten
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if os.path.exists(hipcc):
+        roc = str(d / "pin_rocrand")
+        subprocess.run([hipcc, "-O1", "-std=c++17",
+                        os.path.join(HERE, "pins", "philox_rocrand.cpp"), "-o", roc], check=True)
+        exes["rocrand"] = roc
+    return exes
+
+
+@pytest.mark.parametrize("lib", ["aten", "rocrand"])
+def test_philox_matches_library(pin_exes, lib):
+    if lib not in pin_exes:
+        pytest.skip(f"{lib} pin could not be built here")
+    cases = _counter_cases()
+    ref = _run_pin(pin_exes[lib], cases)
+    got = _oracle_words(cases)
+    assert ref.shape == got.shape
+    assert np.array_equal(ref, got)
+
+
+def test_philox_batch_equals_single():
+    rng = np.random.default_rng(3)
+    ctr = rng.integers(0, 1 << 32, size=(257, 4), dtype=np.uint64).astype(np.uint32)
+    key = [0x12345678, 0x9ABCDEF0]
+    batch = oracle.philox4x32_10(ctr, key)
+    single = np.stack([oracle.philox4x32_10(c[None], key)[0] for c in ctr])
+    assert np.array_equal(batch, single)
+
+
+# --------------------------------------------------------------------------
+# FP32 Box-Muller
+# --------------------------------------------------------------------------
+ALL_ODD = (np.arange(1 << 23, dtype=np.uint64) * 2 + 1).astype(np.uint32)
+
+
+def _ulps(got, ref):
+    ulp = np.spacing(np.abs(ref).astype(np.float32)).astype(np.float64)
+    return np.abs(got.astype(np.float64) - ref) / ulp
+
+
+def test_spec_log_exhaustive_within_3ulp():
+    u = ALL_ODD.astype(np.float64) * 2.0 ** -24
+    L = oracle.spec_log(ALL_ODD)
+    assert np.all(L < 0)
+    assert _ulps(L, np.log(u)).max() <= 3.0
+    # end points of the uniform range
+    assert L[0] == np.float32(-24 * math.log(2)) or abs(L[0] + 24 * math.log(2)) < 2e-6
+    assert abs(float(L[-1]) - math.log1p(-2.0 ** -24)) <= 2.0 ** -48
+
+
+def test_spec_cossin_exhaustive_within_2ulp():
+    th = 2 * np.pi * ALL_ODD.astype(np.float64) * 2.0 ** -24
+    c, s = oracle.spec_cossin(ALL_ODD)
+    assert _ulps(c, np.cos(th)).max() <= 2.0
+    assert _ulps(s, np.sin(th)).max() <= 2.0
+
+
+def test_normal_pair_matches_libm_box_muller():
+    rng = np.random.default_rng(5)
+    words = rng.integers(0, 1 << 32, size=(20000, 2), dtype=np.uint64)
+    words = np.concatenate([words, np.array([[0, 0], [0xFFFFFFFF, 0xFFFFFFFF],
+                                             [0, 0x40000000], [0xFFFFFFFF, 0x20000000]],
+                                            dtype=np.uint64)])
+    for re_, ro in words:
+        zc, zs = oracle.normal_pair(int(re_), int(ro))
+        ue = (2 * (int(re_) >> 9) + 1) * 2.0 ** -24
+        uo = (2 * (int(ro) >> 9) + 1) * 2.0 ** -24
+        rho = math.sqrt(-2 * math.log(ue))
+        for got, ref in ((zc, rho * math.cos(2 * math.pi * uo)),
+                         (zs, rho * math.sin(2 * math.pi * uo))):
+            tol = 5 * float(np.spacing(np.float32(abs(ref)))) + 4 * rho * 2.0 ** -24 * 2e-6
+            assert abs(got - ref) <= tol, (re_, ro, got, ref)
+
+
+def test_omega_matches_f64_reference_and_word_layout():
+    seed = 0xDEADBEEF12345
+    for j in list(range(0, 64)) + [4 * 10 ** 6 + 3, (1 << 34) + 1]:
+        for c in (0, 1, 4, 1000):
+            z = oracle.omega_value(seed, j, c)
+            ref = oracle.omega_f64ref(seed, j, c)
+            assert abs(z - ref) <= 5 * float(np.spacing(np.float32(abs(ref)))) + 1e-12
+    # entry (j, c) uses word j mod 4 of counter (j div 4, c, 0): rows 4q..4q+3
+    # of one column come from one Philox call, paired (0,1) and (2,3)
+    q, c = 11, 3
+    w = oracle.philox4x32_10(np.array([[q, 0, c, 0]], dtype=np.uint32),
+                             [seed & 0xFFFFFFFF, seed >> 32])[0]
+    z01 = oracle.normal_pair(int(w[0]), int(w[1]))
+    z23 = oracle.normal_pair(int(w[2]), int(w[3]))
+    got = [oracle.omega_value(seed, 4 * q + t, c) for t in range(4)]
+    assert got == [z01[0], z01[1], z23[0], z23[1]]
+
+
+def test_omega_statistics():
+    from scipy import stats
+
+    z = oracle.omega_block(1, 0, 1 << 18, 0, 4).ravel().astype(np.float64)
+    assert abs(z.mean()) < 5 / math.sqrt(z.size)
+    assert abs(z.var() - 1.0) < 5 * math.sqrt(2.0 / z.size)
+    assert stats.kstest(z, "norm").pvalue > 1e-4
+    # columns are independent streams: sample correlation near zero
+    Z = oracle.omega_block(1, 0, 1 << 16, 0, 4).astype(np.float64)
+    C = np.corrcoef(Z.T)
+    assert np.abs(C - np.eye(4)).max() < 5 / math.sqrt(Z.shape[0])
+    # neighbouring seeds give unrelated matrices
+    Z2 = oracle.omega_block(2, 0, 1 << 16, 0, 4).astype(np.float64)
+    assert abs(np.corrcoef(Z[:, 0], Z2[:, 0])[0, 1]) < 5 / math.sqrt(Z.shape[0])
+
+
+def test_omega_block_is_slice_of_global():
+    full = oracle.omega_block(9, 0, 300, 0, 40)
+    for row0, n, col0, k in [(0, 300, 0, 40), (3, 101, 7, 5), (1, 1, 39, 1), (257, 43, 0, 16)]:
+        assert np.array_equal(oracle.omega_block(9, row0, n, col0, k),
+                              full[row0:row0 + n, col0:col0 + k])
+
+
+# --------------------------------------------------------------------------
+# Products
+# --------------------------------------------------------------------------
+def test_identity_gives_omega_block():
+    n, k, row0, col0 = 77, 6, 13, 2
+    Y = oracle.gen_matmul(np.eye(n, dtype=np.float32), 4, row0, col0, k)
+    assert np.array_equal(Y, oracle.omega_block(4, row0, n, col0, k).astype(np.float64))
+
+
+def test_selection_matrix_picks_global_rows():
+    m, n, k, row0, col0 = 50, 300, 5, 4096 * 3 + 1, 0
+    S, cols = selection_matrix(m, n, seed=2)
+    Y = oracle.gen_matmul(S, 11, row0, col0, k)
+    for i in range(m):
+        expect = [oracle.omega_value(11, row0 + int(cols[i]), col0 + c) for c in range(k)]
+        assert np.array_equal(Y[i], np.array(expect, dtype=np.float64))
+
+
+def test_matches_numpy_matmul_nonsquare():
+    m, n, k = 37, 203, 9
+    A = normal_matrix(m, n, seed=6)
+    Om = oracle.omega_block(21, 5, n, 3, k)
+    Y = oracle.gen_matmul(A, 21, 5, 3, k)
+    ref = A.astype(np.float64) @ Om.astype(np.float64)
+    assert Y.shape == (m, k)
+    assert np.abs(Y - ref).max() <= 1e-12 * np.abs(A).sum(1).max() * np.abs(Om).max()
+
+
+def test_exactly_rounded_sum_tiny():
+    m, n, k = 5, 17, 3
+    A = normal_matrix(m, n, seed=8)
+    Om = oracle.omega_block(1, 0, n, 0, k)
+    Y = oracle.gen_matmul(A, 1, 0, 0, k)
+    for i in range(m):
+        for c in range(k):
+            terms = [float(A[i, j]) * float(Om[j, c]) for j in range(n)]
+            exact = math.fsum(terms)
+            bound = n * 2.0 ** -53 * sum(abs(t) for t in terms)
+            assert abs(Y[i, c] - exact) <= bound
+
+
+def test_zero_scaling_and_padding():
+    m, n, k = 9, 64, 4
+    A = normal_matrix(m, n, seed=10)
+    assert not oracle.gen_matmul(np.zeros((m, n), np.float32), 3, 0, 0, k).any()
+    Y = oracle.gen_matmul(A, 3, 8, 1, k)
+    assert np.array_equal(oracle.gen_matmul(A * np.float32(4.0), 3, 8, 1, k), 4.0 * Y)
+    # an offset row0 equals zero columns of A in front of the block
+    pad = np.zeros((m, 8 + n), np.float32)
+    pad[:, 8:] = A
+    assert np.array_equal(oracle.gen_matmul(pad, 3, 0, 1, k), Y)
+
+
+def test_strided_view_equals_copy():
+    A = normal_matrix(20, 100, seed=12)
+    view = A[:, 30:70]
+    assert np.array_equal(oracle.gen_matmul(view, 5, 30, 0, 3),
+                          oracle.gen_matmul(np.ascontiguousarray(view), 5, 30, 0, 3))
+
+
+def test_contraction_split_equals_single_product():
+    """Alg. 1 with a (1, P, 1) grid: summing the P partial products over column
+    blocks gives the product of the whole row (up to FP64 rounding)."""
+    m, n, P, k = 33, 4 * 64 + 7, 4, 5
+    A = normal_matrix(m, n, seed=14)
+    bounds = [0, 64, 128, 192, n]
+    blocks = [A[:, bounds[b]:bounds[b + 1]] for b in range(P)]
+    Yred = oracle.gen_matmul_reduce(blocks, bounds[:P], 77, 0, k)
+    Yfull = oracle.gen_matmul(A, 77, 0, 0, k)
+    assert oracle.rel_fro(Yred, Yfull) <= 1e-13
+    # row split (P, 1, 1): the row blocks of Y are the products of the row blocks of A
+    Yrows = np.concatenate([oracle.gen_matmul(A[i:i + 11], 77, 0, 0, k) for i in range(0, m, 11)])
+    assert np.array_equal(Yrows, Yfull)
+
+
+def test_empty_shapes():
+    assert oracle.gen_matmul(np.zeros((0, 5), np.float32), 1, 0, 0, 3).shape == (0, 3)
+    Y = oracle.gen_matmul(np.zeros((4, 0), np.float32), 1, 0, 0, 3)
+    assert Y.shape == (4, 3) and not Y.any()
+
+
+# --------------------------------------------------------------------------
+# Storage formats
+# --------------------------------------------------------------------------
+def test_bf16_matches_torch():
+    import torch
+
+    x = np.concatenate([normal_matrix(1, 5000, 3).ravel(),
+                        np.array([0.0, -0.0, 1.0, 65504.0, 3.0e38, 1e-40, 1.00390625,
+                                  1.01171875, -2.0 ** -130], dtype=np.float32)])
+    ref = torch.from_numpy(x).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
+    assert np.array_equal(oracle.bf16_encode(x), ref)
+    dec = oracle.bf16_decode(ref[:100])
+    assert np.array_equal(dec, torch.from_numpy(ref[:100].view(np.int16)).view(torch.bfloat16)
+                          .float().numpy().astype(np.float64))
+
+
+def test_fp8_codec_matches_torch():
+    import torch
+
+    codes = np.arange(256, dtype=np.uint8)
+    ref = torch.from_numpy(codes).view(torch.float8_e4m3fn).float().numpy().astype(np.float64)
+    table = oracle.fp8_decode_table()
+    nan = np.isnan(ref)
+    assert np.array_equal(nan, np.isnan(table))
+    assert np.array_equal(ref[~nan], table[~nan])
+    rng = np.random.default_rng(4)
+    vals = np.concatenate([rng.standard_normal(4000) * 50, rng.standard_normal(1000) * 1e-3,
+                           table[~nan], (table[~nan][1:] + table[~nan][:-1]) / 2])
+    vals = vals[np.abs(vals) <= 448].astype(np.float32)
+    tref = torch.from_numpy(vals).to(torch.float8_e4m3fn).view(torch.uint8).numpy()
+    got = np.array([oracle.fp8_encode(float(v)) for v in vals], dtype=np.uint8)
+    # +0 and -0 are distinct codes in both
+    assert np.array_equal(got, tref)
+    assert oracle.fp8_encode(1000.0) == 0x7E and oracle.fp8_encode(-1e9) == 0xFE
+
+
+def test_fp8_rows128_scales_definition():
+    A = normal_matrix(300, 40, seed=15) * np.float32(3.0)
+    A[128:256] *= np.float32(1e-3)
+    A[256:] = 0.0
+    Q, s = oracle.quantize_fp8_rows128(A)
+    assert s.shape == (3,)
+    for b in range(2):
+        amax = float(np.abs(A[128 * b:128 * (b + 1)]).max())
+        E = math.log2(float(s[b]))
+        assert E == int(E)
+        assert amax <= 448 * s[b] and amax > 448 * s[b] / 2
+    assert s[2] == 1.0 and not Q[256:].any()
+    table = oracle.fp8_decode_table()
+    deq = table[Q] * np.repeat(s.astype(np.float64), 128)[:300, None]
+    rel = np.abs(deq - A) / np.maximum(np.abs(A), 1e-30)
+    mask = np.abs(A) >= 2.0 ** -6 * np.repeat(s, 128)[:300, None]
+    assert rel[mask].max() <= 2.0 ** -4 + 1e-12   # 3 mantissa bits, round to nearest
+
+
+def test_quantized_product_equals_product_of_dequantized():
+    m, n, k = 130, 96, 5
+    A = normal_matrix(m, n, seed=16)
+    Qb = oracle.bf16_encode(A)
+    Ab = oracle.bf16_decode(Qb).astype(np.float32)
+    assert np.array_equal(oracle.gen_matmul_q(Qb, "bf16", None, 2, 0, 0, k),
+                          oracle.gen_matmul(Ab, 2, 0, 0, k))
+    Q8, s = oracle.quantize_fp8_rows128(A)
+    A8 = (oracle.fp8_decode_table()[Q8] * np.repeat(s.astype(np.float64), 128)[:m, None])
+    assert np.array_equal(oracle.gen_matmul_q(Q8, "fp8", s, 2, 0, 0, k),
+                          oracle.gen_matmul(A8.astype(np.float32), 2, 0, 0, k))
+
+
+# --------------------------------------------------------------------------
+# Golden fixtures (written by tests/golden/make_golden.py from the oracle)
+# --------------------------------------------------------------------------
+GOLDEN = os.path.join(HERE, "golden")
+
+
+def _golden_rows(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return [line.split() for line in f if not line.startswith("#")]
+
+
+def test_golden_omega_block():
+    rows = _golden_rows("omega_seed1_r0-63_c0-4.txt")
+    ref = np.array([[int(w, 16) for w in r] for r in rows], dtype=np.uint32)
+    assert np.array_equal(oracle.omega_block(1, 0, 64, 0, 5).view(np.uint32), ref)
+
+
+def test_golden_omega_offsets():
+    for r, c, bits in _golden_rows("omega_seed2026_offsets.txt"):
+        got = np.float32(oracle.omega_value(2026, int(r), int(c))).view(np.uint32)
+        assert int(got) == int(bits, 16)
