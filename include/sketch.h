@@ -1,0 +1,193 @@
+/*
+ * sketch.h -- C ABI of the MI355X (gfx950) library for the sketch
+ *
+ *     Y = A * Omega(seed)
+ *
+ * where Omega is a dense N(0,1) random matrix that is never stored: every
+ * call regenerates the entries it needs from a 64-bit seed with a
+ * counter-based Philox4x32-10 generator, inside the multiply kernel.
+ *
+ * Paper: "Communication Lower Bounds and Algorithms for Sketching with Random
+ * Dense Matrices" (SPAA '26).
+ *   - Problem: B = A*Omega, A n1 x n2, Omega n2 x r random, r < n2 (Sec. 4).
+ *   - Alg. 1 (RandMatMul): processor (i,j,k) generates the (j,k) block of the
+ *     global Omega (GenRandom), multiplies its A block by it, and the partial
+ *     products of a contraction split are summed (Reduce-Scatter).
+ *   - Sec. 4.3 Case 1 (row split, p1 = P): no communication at all; every
+ *     process regenerates the whole Omega from the shared seed (Sec. 6.3/6.4).
+ *   - Sec. 6.3: Omega is produced by the counter-based Philox generator
+ *     (Salmon et al., SC'11) rather than communicated.
+ *
+ * Omega is defined entry by entry (readings of the paper documented with the
+ * library): Omega(j, c) for global row j and column c is word (j mod 4) of
+ * Philox4x32-10 applied to the counter (q mod 2^32, q div 2^32, c, 0) with
+ * q = j div 4 and key (seed mod 2^32, seed div 2^32); each word r gives
+ * u = (2 (r >> 9) + 1) 2^-24, words (0,1) and (2,3) are Box-Muller pairs
+ * (rho cos, rho sin) with rho from the even word and angle 2 pi u from the
+ * odd word, evaluated by a fixed FP32 operation sequence so that the values
+ * are reproducible bit for bit on any IEEE machine.
+ *
+ * Conventions for every call below:
+ *   - Matrices are row-major: element (i, j) of A sits at A + i*lda + j
+ *     (in elements of A's storage type); Y(i, c) sits at Y + i*ldy + c.
+ *   - All buffer pointers are DEVICE pointers unless stated, owned by the
+ *     caller; the library never allocates or frees memory in these calls.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Calls only
+ *     enqueue work; they never synchronise the host.
+ *   - Argument errors are detected on the host before anything is enqueued;
+ *     on such an error nothing is written.  SK_EHIP reports a failed launch.
+ *   - Results do not depend on the launch configuration: for a given A,
+ *     seed, offsets and k, Y is bitwise reproducible run to run, and equal
+ *     between a call on a row block and the matching rows of a call on the
+ *     whole matrix.
+ */
+#ifndef SKETCH_H
+#define SKETCH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SKETCH_ABI_VERSION 1
+
+enum sk_status {
+    SK_OK = 0,
+    SK_EINVAL = -1,        /* bad size, pointer, leading dimension or flag       */
+    SK_EDTYPE = -2,        /* unknown element type                                */
+    SK_EALIGN = -3,        /* A or lda not aligned to 16 bytes (see below)        */
+    SK_EWORKSPACE = -4,    /* workspace missing or smaller than required          */
+    SK_EHIP = -5,          /* HIP runtime reported an error at launch             */
+    SK_ENOMEM = -6,        /* (serving) device memory exhausted                   */
+    SK_EUNSUPPORTED = -7,  /* valid request this build does not handle            */
+    SK_EBUDGET = -8,       /* (serving) request larger than the memory budget     */
+    SK_EQUEUE = -9         /* (serving) queue full or unknown ticket              */
+};
+
+/* Storage type of A. */
+enum sk_adtype {
+    SK_A_F32 = 0,          /* IEEE binary32                                       */
+    SK_A_BF16 = 1,         /* bfloat16                                            */
+    SK_A_FP8_E4M3 = 2      /* OCP FP8 E4M3FN, with per-128-row-block scales       */
+};
+
+/* Storage type of Y.  The reduction over column strips and blocks is carried
+ * out in FP64 and rounded once to the output type. */
+enum sk_ydtype { SK_Y_F32 = 0, SK_Y_F64 = 1 };
+
+/* Version of this ABI (SKETCH_ABI_VERSION of the built library). */
+int sketch_abi_version(void);
+
+/* Static text for a status code. */
+const char* sketch_status_string(int status);
+
+/* Bytes of device workspace a call needs (0 if none).
+ *   op = 0: sketch_gen_matmul / sketch_matmul_omega with an n-column A;
+ *   op = 1: sketch_gen_matmul_reduce over P blocks whose widths sum to n.
+ * The size depends only on (op, a_dtype, m, n, k, P); for op = 1 it is an
+ * upper bound valid for any split of n into P blocks.  Returns 0 for
+ * invalid arguments. */
+size_t sketch_workspace_size(int op, int a_dtype, int64_t m, int64_t n, int64_t k, int64_t P);
+
+/* Prepare a workspace for first use: zero its `bytes` bytes on `stream`.
+ * A workspace must be prepared once after allocation (or be allocated zeroed);
+ * every call that completes leaves it prepared again.  One workspace serves
+ * one call at a time: calls that overlap in time need separate workspaces. */
+int sketch_workspace_init(void* workspace, size_t bytes, void* stream);
+
+/*
+ * The local product of one process's share (Alg. 1, local multiplication with
+ * GenRandom; Sec. 4.3 Case 1 for a row block):
+ *
+ *   Y[0:m, 0:k] (=|+=) A[0:m, 0:n] * Omega(seed)[row0 : row0+n, col0 : col0+k]
+ *
+ *   A          device, m x n, storage a_dtype, leading dim lda (elements).
+ *              Alignment: A and lda*sizeof(element) must be multiples of 16 B.
+ *   a_scales   device, ceil(m/128) FP32 scales for SK_A_FP8_E4M3 (row i uses
+ *              a_scales[i/128]); NULL for F32/BF16 (scale 1).
+ *   seed       the shared seed of the global Omega.
+ *   omega_row0 global row of Omega matching column 0 of A (0 <= row0, row0+n <= 2^62).
+ *   omega_col0 global column of Omega matching column 0 of Y (col0+k <= 2^32).
+ *   k          sketch width, 1 <= k <= 256.
+ *   Y          device, m x k, storage y_dtype, leading dim ldy >= k.
+ *   beta       0: Y = A*Omega;  1: Y = Y + A*Omega (old Y added in FP64).
+ *   workspace  device, >= sketch_workspace_size(0, a_dtype, m, n, k, 1) bytes,
+ *              prepared (see sketch_workspace_init); may be NULL if that size is 0.
+ * m == 0 or k == 0: nothing to do.  n == 0: Y = 0 (beta 0) or unchanged.
+ */
+int sketch_gen_matmul(const void* A, int a_dtype, int64_t m, int64_t n, int64_t lda,
+                      const float* a_scales, uint64_t seed, int64_t omega_row0,
+                      int64_t omega_col0, int64_t k, void* Y, int y_dtype, int64_t ldy,
+                      int beta, void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * Contraction split with on-device reduction (Alg. 1 on a (1, P, 1) grid: the
+ * local products of P column blocks followed by the sum that Reduce-Scatter /
+ * AllReduce performs across processes, Sec. 4.3 and Sec. 6.5), done in one
+ * launch on one device:
+ *
+ *   Y (=|+=) sum_{b=0}^{P-1} A_b[0:m, 0:n_b] * Omega(seed)[row0_b : row0_b+n_b, col0 : col0+k]
+ *
+ *   A_b, n_b, lda_b, row0_b, a_scales_b  HOST arrays of length P describing the
+ *              blocks (device pointers A_b[b]; a_scales_b may be NULL, or hold
+ *              NULL entries, for F32/BF16).  1 <= P <= 64.
+ *   The partial products are summed in FP64 in block order b = 0..P-1 and
+ *   rounded once to y_dtype.  Other arguments as for sketch_gen_matmul; the
+ *   workspace must hold sketch_workspace_size(1, a_dtype, m, sum n_b, k, P).
+ * When each block's width is a multiple of 1024 and row0_b = row0_0 + the
+ * block's column offset, the result equals bitwise that of sketch_gen_matmul
+ * on the concatenated A.
+ */
+int sketch_gen_matmul_reduce(const void* const* A_b, int64_t P, int a_dtype, int64_t m,
+                             const int64_t* n_b, const int64_t* lda_b, const int64_t* row0_b,
+                             const float* const* a_scales_b, uint64_t seed, int64_t omega_col0,
+                             int64_t k, void* Y, int y_dtype, int64_t ldy, int beta,
+                             void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * Materialise Omega(seed)[row0 : row0+n, col0 : col0+k] into device memory
+ * (n x k FP32, leading dim ldo >= k).  This is the "communicate Omega"
+ * alternative of Sec. 6.3 on one device (the operand stored in HBM instead of
+ * regenerated); the generated-operand calls above never use it.
+ */
+int sketch_gen_omega(uint64_t seed, int64_t row0, int64_t n, int64_t col0, int64_t k,
+                     float* Omega, int64_t ldo, void* stream);
+
+/*
+ * Y (=|+=) A * Omega for an explicit Omega in device memory (n x k FP32,
+ * leading dim ldo >= k): the stored-operand counterpart of sketch_gen_matmul
+ * (Sec. 6.3), with the same blocking and summation order, so that it returns
+ * bitwise the same Y when Omega holds the generated values.  Arguments as for
+ * sketch_gen_matmul (workspace op = 0).
+ */
+int sketch_matmul_omega(const void* A, int a_dtype, int64_t m, int64_t n, int64_t lda,
+                        const float* a_scales, const float* Omega, int64_t ldo, int64_t k,
+                        void* Y, int y_dtype, int64_t ldy, int beta, void* workspace,
+                        size_t workspace_bytes, void* stream);
+
+/*
+ * Raw Philox4x32-10 stream (Sec. 6.3 generator): out[4i .. 4i+3] =
+ * Philox4x32-10(ctr[4i .. 4i+3], key = (seed mod 2^32, seed div 2^32)),
+ * 0 <= i < N.  ctr and out are device arrays of 4N uint32.
+ */
+int sketch_philox_raw(const uint32_t* ctr, uint64_t seed, uint32_t* out, int64_t N,
+                      void* stream);
+
+/*
+ * Low-precision storage of A (precision form; untimed preprocessing):
+ *   dst_dtype SK_A_BF16: Aq = bf16(A), round to nearest even; scales unused.
+ *   dst_dtype SK_A_FP8_E4M3: for each 128-row block b, s_b = the smallest
+ *     power of two 2^E with max|A(block)| <= 448 2^E (1 for an all-zero
+ *     block); Aq(i, j) = e4m3(A(i, j) / s_b), round to nearest even,
+ *     saturating at +-448; scales[b] = s_b (ceil(m/128) floats).
+ *   ldq in elements of the destination type; Aq and ldq*size 16-B aligned.
+ */
+int sketch_quantize(const float* A, int64_t m, int64_t n, int64_t lda, int dst_dtype, void* Aq,
+                    int64_t ldq, float* scales, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SKETCH_H */

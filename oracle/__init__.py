@@ -66,8 +66,14 @@ def _load():
     lib.oracle_quantize_fp8_rows128.argtypes = [P, i64, i64, i64, P, i64, P]
     lib.oracle_gen_matmul_q_f64.argtypes = [P, ctypes.c_int, i64, i64, i64, P, u64, i64, i64,
                                             i64, P]
+    lib.oracle_num_threads.restype = ctypes.c_int
     _lib = lib
     return lib
+
+
+def num_threads() -> int:
+    """Threads used by the oracle's OpenMP loops."""
+    return int(_load().oracle_num_threads())
 
 
 def _ptr(a: np.ndarray):

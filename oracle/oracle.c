@@ -27,6 +27,9 @@
 #include "oracle.h"
 
 #include <float.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -378,4 +381,13 @@ void oracle_gen_matmul_q_f64(const void* Aq, int dtype, int64_t m, int64_t n, in
         }
     }
     free(Om);
+}
+
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }

@@ -83,6 +83,9 @@ void oracle_gen_matmul_q_f64(const void* Aq, int dtype, int64_t m, int64_t n, in
                              const float* scales, uint64_t seed, int64_t row0, int64_t col0,
                              int64_t k, double* Y);
 
+/* Threads the oracle's parallel loops use (OpenMP). */
+int oracle_num_threads(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,299 @@
+"""MI355X (gfx950) library for the sketch Y = A * Omega(seed) with a generated operand.
+
+Python binding of the C ABI in ``include/sketch.h`` (libsketch.so, built by
+``paper_2603_20966_amd.build``).  The functions carry the ABI's names and only
+marshal arguments: torch tensors give device pointers and the current HIP
+stream; every step of the computation runs in the library's kernels.  There is
+no fallback: if the library is not built, every call raises.
+
+Paper: "Communication Lower Bounds and Algorithms for Sketching with Random
+Dense Matrices" (SPAA '26): Sec. 4 (B = A*Omega), Alg. 1 (GenRandom, local
+product, Reduce-Scatter of a contraction split), Sec. 6.3 (Philox; Omega
+generated instead of communicated).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsketch.so")
+
+SK_A_F32, SK_A_BF16, SK_A_FP8_E4M3 = 0, 1, 2
+SK_Y_F32, SK_Y_F64 = 0, 1
+STATUS = {0: "SK_OK", -1: "SK_EINVAL", -2: "SK_EDTYPE", -3: "SK_EALIGN", -4: "SK_EWORKSPACE",
+          -5: "SK_EHIP", -6: "SK_ENOMEM", -7: "SK_EUNSUPPORTED", -8: "SK_EBUDGET",
+          -9: "SK_EQUEUE"}
+
+_lib = None
+_lock = threading.Lock()
+
+
+class SketchError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = sketch_status_string(status) if _lib is not None else ""
+        super().__init__(f"{where}: {STATUS.get(status, status)} ({msg})")
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libsketch.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run paper_2603_20966_amd.build.build() "
+                               "(the HIP library is required; there is no CPU fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i64, u64, sz, i32 = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_size_t,
+                                ctypes.c_int)
+        L.sketch_abi_version.argtypes = []
+        L.sketch_abi_version.restype = i32
+        L.sketch_status_string.argtypes = [i32]
+        L.sketch_status_string.restype = ctypes.c_char_p
+        L.sketch_workspace_size.argtypes = [i32, i32, i64, i64, i64, i64]
+        L.sketch_workspace_size.restype = sz
+        L.sketch_workspace_init.argtypes = [P, sz, P]
+        L.sketch_gen_matmul.argtypes = [P, i32, i64, i64, i64, P, u64, i64, i64, i64, P, i32, i64,
+                                        i32, P, sz, P]
+        L.sketch_gen_matmul_reduce.argtypes = [P, i64, i32, i64, P, P, P, P, u64, i64, i64, P, i32,
+                                               i64, i32, P, sz, P]
+        L.sketch_gen_omega.argtypes = [u64, i64, i64, i64, i64, P, i64, P]
+        L.sketch_matmul_omega.argtypes = [P, i32, i64, i64, i64, P, P, i64, i64, P, i32, i64, i32,
+                                          P, sz, P]
+        L.sketch_philox_raw.argtypes = [P, u64, P, i64, P]
+        L.sketch_quantize.argtypes = [P, i64, i64, i64, i32, P, i64, P, P]
+        for f in ("sketch_workspace_init", "sketch_gen_matmul", "sketch_gen_matmul_reduce",
+                  "sketch_gen_omega", "sketch_matmul_omega", "sketch_philox_raw",
+                  "sketch_quantize"):
+            getattr(L, f).restype = i32
+        _lib = L
+        return L
+
+
+def _check(status: int, where: str) -> None:
+    if status != 0:
+        raise SketchError(status, where)
+
+
+def sketch_abi_version() -> int:
+    return int(lib().sketch_abi_version())
+
+
+def sketch_status_string(status: int) -> str:
+    return lib().sketch_status_string(int(status)).decode()
+
+
+# ----------------------------------------------------------------------------
+# marshalling helpers
+# ----------------------------------------------------------------------------
+def _adtype(t: torch.Tensor) -> int:
+    if t.dtype == torch.float32:
+        return SK_A_F32
+    if t.dtype == torch.bfloat16:
+        return SK_A_BF16
+    if t.dtype in (torch.uint8, torch.float8_e4m3fn):
+        return SK_A_FP8_E4M3
+    raise TypeError(f"unsupported A dtype {t.dtype}")
+
+
+def _ydtype(dt) -> int:
+    if dt == torch.float32:
+        return SK_Y_F32
+    if dt == torch.float64:
+        return SK_Y_F64
+    raise TypeError(f"unsupported Y dtype {dt}")
+
+
+def _ld(t: torch.Tensor, name: str) -> int:
+    if t.dim() != 2:
+        raise ValueError(f"{name} must be 2-D")
+    if t.shape[1] > 1 and t.stride(1) != 1:
+        raise ValueError(f"{name} must have unit column stride")
+    return int(t.stride(0))
+
+
+def _stream(stream, device) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else int(t.data_ptr())
+
+
+_ws_cache: dict = {}
+
+
+def workspace_for(nbytes: int, device, stream_ptr: int) -> tuple[int, int]:
+    """A prepared (zeroed) workspace of at least nbytes for (device, stream).
+
+    The library leaves a workspace prepared after every completed call, so the
+    cached buffer is reused as is; calls on one stream never overlap in time.
+    """
+    if nbytes == 0:
+        return 0, 0
+    key = (torch.device(device).index, stream_ptr)
+    buf = _ws_cache.get(key)
+    if buf is None or buf.numel() < nbytes:
+        buf = torch.zeros(max(nbytes, 1 << 20), dtype=torch.uint8, device=device)
+        _ws_cache[key] = buf
+    return int(buf.data_ptr()), int(buf.numel())
+
+
+# ----------------------------------------------------------------------------
+# ABI calls
+# ----------------------------------------------------------------------------
+def sketch_workspace_size(op: int, a_dtype: int, m: int, n: int, k: int, P: int = 1) -> int:
+    return int(lib().sketch_workspace_size(op, a_dtype, m, n, k, P))
+
+
+def sketch_workspace_init(ws: torch.Tensor, stream=None) -> None:
+    _check(lib().sketch_workspace_init(_ptr(ws), ws.numel() * ws.element_size(),
+                                       _stream(stream, ws.device)), "sketch_workspace_init")
+
+
+def _out(Y, m, k, y_dtype, device):
+    if Y is None:
+        return torch.empty((m, k), dtype=y_dtype, device=device)
+    return Y
+
+
+def sketch_gen_matmul(A: torch.Tensor, seed: int, k: int, *, omega_row0: int = 0,
+                      omega_col0: int = 0, Y: torch.Tensor | None = None, beta: int = 0,
+                      a_scales: torch.Tensor | None = None, y_dtype=torch.float32,
+                      workspace: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Y (=|+=) A * Omega(seed)[row0:row0+n, col0:col0+k] (one share, Alg. 1 local product)."""
+    m, n = A.shape
+    lda = _ld(A, "A") if m > 0 else max(n, 1)
+    Y = _out(Y, m, k, y_dtype if Y is None else Y.dtype, A.device)
+    ldy = _ld(Y, "Y") if m > 0 else max(k, 1)
+    st = _stream(stream, A.device)
+    adt = _adtype(A)
+    need = sketch_workspace_size(0, adt, m, n, k, 1)
+    if workspace is not None:
+        wsp, wsb = _ptr(workspace), workspace.numel() * workspace.element_size()
+    else:
+        wsp, wsb = workspace_for(need, A.device, st)
+    _check(lib().sketch_gen_matmul(_ptr(A), adt, m, n, lda, _ptr(a_scales), seed, omega_row0,
+                                   omega_col0, k, _ptr(Y), _ydtype(Y.dtype), ldy, beta, wsp, wsb,
+                                   st), "sketch_gen_matmul")
+    return Y
+
+
+def sketch_gen_matmul_reduce(blocks, row0s, seed: int, k: int, *, omega_col0: int = 0,
+                             Y: torch.Tensor | None = None, beta: int = 0, scales=None,
+                             y_dtype=torch.float32, workspace: torch.Tensor | None = None,
+                             stream=None) -> torch.Tensor:
+    """Y (=|+=) sum_b A_b * Omega[row0_b:row0_b+n_b, col0:col0+k] (1Dred share, device FP64 sum)."""
+    P = len(blocks)
+    if P == 0 or len(row0s) != P:
+        raise ValueError("need one row offset per block")
+    m = blocks[0].shape[0]
+    dev = blocks[0].device
+    adt = _adtype(blocks[0])
+    Y = _out(Y, m, k, y_dtype if Y is None else Y.dtype, dev)
+    ldy = _ld(Y, "Y") if m > 0 else max(k, 1)
+    ptrs = (ctypes.c_void_p * P)(*[b.data_ptr() for b in blocks])
+    nb = (ctypes.c_int64 * P)(*[int(b.shape[1]) for b in blocks])
+    ld = (ctypes.c_int64 * P)(*[(_ld(b, "A_b") if m > 0 else max(int(b.shape[1]), 1))
+                                for b in blocks])
+    r0 = (ctypes.c_int64 * P)(*[int(r) for r in row0s])
+    sc = None
+    if scales is not None:
+        sc = (ctypes.c_void_p * P)(*[(s.data_ptr() if s is not None else None) for s in scales])
+    st = _stream(stream, dev)
+    need = sketch_workspace_size(1, adt, m, sum(int(b.shape[1]) for b in blocks), k, P)
+    if workspace is not None:
+        wsp, wsb = _ptr(workspace), workspace.numel() * workspace.element_size()
+    else:
+        wsp, wsb = workspace_for(need, dev, st)
+    _check(lib().sketch_gen_matmul_reduce(ptrs, P, adt, m, nb, ld, r0, sc, seed, omega_col0, k,
+                                          _ptr(Y), _ydtype(Y.dtype), ldy, beta, wsp, wsb, st),
+           "sketch_gen_matmul_reduce")
+    return Y
+
+
+def sketch_gen_omega(seed: int, row0: int, n: int, col0: int, k: int, *,
+                     out: torch.Tensor | None = None, device="cuda", stream=None) -> torch.Tensor:
+    """Omega(seed)[row0:row0+n, col0:col0+k] materialised (stored-operand alternative)."""
+    if out is None:
+        out = torch.empty((n, k), dtype=torch.float32, device=device)
+    ldo = _ld(out, "Omega") if n > 0 else max(k, 1)
+    _check(lib().sketch_gen_omega(seed, row0, n, col0, k, _ptr(out), ldo,
+                                  _stream(stream, out.device)), "sketch_gen_omega")
+    return out
+
+
+def sketch_matmul_omega(A: torch.Tensor, Omega: torch.Tensor, *, Y: torch.Tensor | None = None,
+                        beta: int = 0, a_scales: torch.Tensor | None = None,
+                        y_dtype=torch.float32, workspace: torch.Tensor | None = None,
+                        stream=None) -> torch.Tensor:
+    """Y (=|+=) A * Omega with Omega read from device memory (same order as the generated path)."""
+    m, n = A.shape
+    k = Omega.shape[1]
+    if Omega.shape[0] != n:
+        raise ValueError("Omega must have n rows")
+    lda = _ld(A, "A") if m > 0 else max(n, 1)
+    ldo = _ld(Omega, "Omega") if n > 0 else max(k, 1)
+    Y = _out(Y, m, k, y_dtype if Y is None else Y.dtype, A.device)
+    ldy = _ld(Y, "Y") if m > 0 else max(k, 1)
+    st = _stream(stream, A.device)
+    adt = _adtype(A)
+    need = sketch_workspace_size(0, adt, m, n, k, 1)
+    if workspace is not None:
+        wsp, wsb = _ptr(workspace), workspace.numel() * workspace.element_size()
+    else:
+        wsp, wsb = workspace_for(need, A.device, st)
+    _check(lib().sketch_matmul_omega(_ptr(A), adt, m, n, lda, _ptr(a_scales), _ptr(Omega), ldo, k,
+                                     _ptr(Y), _ydtype(Y.dtype), ldy, beta, wsp, wsb, st),
+           "sketch_matmul_omega")
+    return Y
+
+
+def sketch_philox_raw(ctr: torch.Tensor, seed: int, *, out: torch.Tensor | None = None,
+                      stream=None) -> torch.Tensor:
+    """Philox4x32-10 of each row of ctr (N x 4 int32/uint32 device tensor) under key = seed."""
+    if ctr.dim() != 2 or ctr.shape[1] != 4 or not ctr.is_contiguous():
+        raise ValueError("ctr must be a contiguous N x 4 tensor")
+    if out is None:
+        out = torch.empty_like(ctr)
+    _check(lib().sketch_philox_raw(_ptr(ctr), seed, _ptr(out), ctr.shape[0],
+                                   _stream(stream, ctr.device)), "sketch_philox_raw")
+    return out
+
+
+def sketch_quantize(A: torch.Tensor, dst: str, *, stream=None):
+    """Low-precision copy of A: ('bf16' -> (Aq bfloat16, None)); ('fp8' -> (Aq uint8 codes, scales))."""
+    m, n = A.shape
+    lda = _ld(A, "A") if m > 0 else max(n, 1)
+    st = _stream(stream, A.device)
+    if dst == "bf16":
+        Aq = torch.empty((m, n), dtype=torch.bfloat16, device=A.device)
+        if n % 8:
+            Aq = torch.empty((m, (n + 7) // 8 * 8), dtype=torch.bfloat16, device=A.device)[:, :n]
+        _check(lib().sketch_quantize(_ptr(A), m, n, lda, SK_A_BF16, _ptr(Aq),
+                                     _ld(Aq, "Aq") if m > 0 else max(n, 1), None, st),
+               "sketch_quantize")
+        return Aq, None
+    if dst == "fp8":
+        ldq = (n + 15) // 16 * 16
+        Aq = torch.empty((m, max(ldq, 16)), dtype=torch.uint8, device=A.device)[:, :n]
+        scales = torch.empty(((m + 127) // 128,), dtype=torch.float32, device=A.device)
+        _check(lib().sketch_quantize(_ptr(A), m, n, lda, SK_A_FP8_E4M3, _ptr(Aq), max(ldq, 16),
+                                     _ptr(scales), st), "sketch_quantize")
+        return Aq, scales
+    raise ValueError("dst must be 'bf16' or 'fp8'")
+
+
+__all__ = ["sketch_abi_version", "sketch_status_string", "sketch_workspace_size",
+           "sketch_workspace_init", "sketch_gen_matmul", "sketch_gen_matmul_reduce",
+           "sketch_gen_omega", "sketch_matmul_omega", "sketch_philox_raw", "sketch_quantize",
+           "SketchError", "lib", "LIB_PATH"]

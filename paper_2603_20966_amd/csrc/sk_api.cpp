@@ -1,0 +1,243 @@
+// C ABI of the sketch library: argument validation and dispatch.  Every
+// argument error is returned before anything is enqueued.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+#include <string.h>
+
+#include "../../include/sketch.h"
+#include "sk_internal.hpp"
+
+namespace {
+
+constexpr int64_t kMaxRow = (int64_t)1 << 62;
+constexpr int64_t kMaxCol = (int64_t)1 << 32;
+constexpr int64_t kMaxK = 256;
+constexpr int64_t kMaxGridY = 65535;
+
+int elem_size(int a_dtype) { return a_dtype == SK_A_F32 ? 4 : a_dtype == SK_A_BF16 ? 2 : 1; }
+bool adtype_ok(int t) { return t == SK_A_F32 || t == SK_A_BF16 || t == SK_A_FP8_E4M3; }
+bool ydtype_ok(int t) { return t == SK_Y_F32 || t == SK_Y_F64; }
+bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+int from_hip(hipError_t e) { return e == hipSuccess ? SK_OK : SK_EHIP; }
+
+// Checks shared by every product call; fills the Y part of the launch.
+int check_common(int a_dtype, int64_t m, int64_t k, int64_t col0, const void* Y, int y_dtype,
+                 int64_t ldy, int beta) {
+    if (!adtype_ok(a_dtype) || !ydtype_ok(y_dtype)) return SK_EDTYPE;
+    if (m < 0 || k < 0 || k > kMaxK) return SK_EINVAL;
+    if (beta != 0 && beta != 1) return SK_EINVAL;
+    if (col0 < 0 || col0 + k > kMaxCol) return SK_EINVAL;
+    if (m == 0 || k == 0) return SK_OK;
+    if (Y == nullptr || ldy < k) return SK_EINVAL;
+    if (((uintptr_t)Y & (y_dtype == SK_Y_F64 ? 7u : 3u)) != 0) return SK_EALIGN;
+    // grid: rows per workgroup are at most 1024, row blocks at most 65535
+    if (m > kMaxGridY * 1024) return SK_EUNSUPPORTED;
+    return SK_OK;
+}
+
+int check_block(const void* A, int a_dtype, int64_t m, int64_t n, int64_t lda, int64_t row0,
+                const float* scales) {
+    if (n < 0 || row0 < 0 || row0 > kMaxRow - n) return SK_EINVAL;
+    if (n == 0 || m == 0) return SK_OK;
+    if (A == nullptr || lda < n) return SK_EINVAL;
+    if (!aligned16(A) || (lda * elem_size(a_dtype)) % 16 != 0) return SK_EALIGN;
+    if (a_dtype == SK_A_FP8_E4M3 && scales == nullptr) return SK_EINVAL;
+    if (scales && ((uintptr_t)scales & 3u)) return SK_EALIGN;
+    return SK_OK;
+}
+
+size_t workspace_for(int op, int64_t m, int64_t n, int64_t k, int64_t P) {
+    const int64_t C = sk::strip_width_for_k(k);
+    const int64_t S = (op == 0) ? (n + C - 1) / C : n / C + P;
+    return sk::gemm_workspace_bytes(m, S, k);
+}
+
+int check_workspace(size_t need, const void* ws, size_t bytes) {
+    if (need == 0) return SK_OK;
+    if (ws == nullptr || bytes < need) return SK_EWORKSPACE;
+    if (!aligned16(ws)) return SK_EALIGN;
+    return SK_OK;
+}
+
+int run_product(sk::GemmLaunch& g, int64_t n_total) {
+    if (g.m == 0 || g.k == 0) return SK_OK;
+    if (n_total == 0) {
+        if (g.beta) return SK_OK;
+        return from_hip(sk::launch_zero_matrix(g.Y, g.y_f64, g.m, g.k, g.ldy, g.stream));
+    }
+    return from_hip(sk::launch_gemm_stream(g));
+}
+
+}  // namespace
+
+extern "C" {
+
+int sketch_abi_version(void) { return SKETCH_ABI_VERSION; }
+
+const char* sketch_status_string(int status) {
+    switch (status) {
+    case SK_OK: return "ok";
+    case SK_EINVAL: return "invalid argument (size, pointer, leading dimension or flag)";
+    case SK_EDTYPE: return "unknown element type";
+    case SK_EALIGN: return "misaligned pointer or leading dimension (16 bytes needed)";
+    case SK_EWORKSPACE: return "workspace missing or too small";
+    case SK_EHIP: return "HIP runtime error";
+    case SK_ENOMEM: return "out of device memory";
+    case SK_EUNSUPPORTED: return "unsupported request";
+    case SK_EBUDGET: return "request exceeds the memory budget";
+    case SK_EQUEUE: return "queue full or unknown ticket";
+    default: return "unknown status";
+    }
+}
+
+size_t sketch_workspace_size(int op, int a_dtype, int64_t m, int64_t n, int64_t k, int64_t P) {
+    if ((op != 0 && op != 1) || !adtype_ok(a_dtype) || m < 0 || n < 0 || k < 0 || k > kMaxK)
+        return 0;
+    if (op == 0) P = 1;
+    if (P < 1 || P > sk::kMaxBlocks || m == 0 || k == 0 || n == 0) return 0;
+    return workspace_for(op, m, n, k, P);
+}
+
+int sketch_workspace_init(void* workspace, size_t bytes, void* stream) {
+    if (bytes == 0) return SK_OK;
+    if (workspace == nullptr) return SK_EINVAL;
+    return from_hip(sk::launch_zero(workspace, bytes, static_cast<hipStream_t>(stream)));
+}
+
+static int gen_matmul_impl(const void* A, int a_dtype, int64_t m, int64_t n, int64_t lda,
+                           const float* a_scales, uint64_t seed, int64_t omega_row0,
+                           int64_t omega_col0, const float* Omega, int64_t ldo, int64_t k,
+                           void* Y, int y_dtype, int64_t ldy, int beta, void* workspace,
+                           size_t workspace_bytes, void* stream) {
+    int st = check_common(a_dtype, m, k, omega_col0, Y, y_dtype, ldy, beta);
+    if (st != SK_OK) return st;
+    st = check_block(A, a_dtype, m, n, lda, omega_row0, a_scales);
+    if (st != SK_OK) return st;
+    if (m == 0 || k == 0) return SK_OK;
+    if (Omega != nullptr || ldo != 0) {
+        if (n > 0 && (Omega == nullptr || ldo < k)) return SK_EINVAL;
+        if (((uintptr_t)Omega & 3u) != 0) return SK_EALIGN;
+    }
+    st = check_workspace(n > 0 ? workspace_for(0, m, n, k, 1) : 0, workspace, workspace_bytes);
+    if (st != SK_OK) return st;
+    sk::GemmLaunch g{};
+    g.adtype = a_dtype;
+    g.m = m;
+    g.P = 1;
+    g.blk[0] = sk::BlockDesc{A, n, lda, omega_row0, a_scales};
+    g.k = k;
+    g.col0 = (uint32_t)omega_col0;
+    g.seed = seed;
+    g.omega = Omega;
+    g.ldo = ldo;
+    g.Y = Y;
+    g.y_f64 = (y_dtype == SK_Y_F64);
+    g.ldy = ldy;
+    g.beta = beta;
+    g.workspace = workspace;
+    g.workspace_bytes = workspace_bytes;
+    g.stream = static_cast<hipStream_t>(stream);
+    return run_product(g, n);
+}
+
+int sketch_gen_matmul(const void* A, int a_dtype, int64_t m, int64_t n, int64_t lda,
+                      const float* a_scales, uint64_t seed, int64_t omega_row0,
+                      int64_t omega_col0, int64_t k, void* Y, int y_dtype, int64_t ldy,
+                      int beta, void* workspace, size_t workspace_bytes, void* stream) {
+    return gen_matmul_impl(A, a_dtype, m, n, lda, a_scales, seed, omega_row0, omega_col0,
+                           nullptr, 0, k, Y, y_dtype, ldy, beta, workspace, workspace_bytes,
+                           stream);
+}
+
+int sketch_matmul_omega(const void* A, int a_dtype, int64_t m, int64_t n, int64_t lda,
+                        const float* a_scales, const float* Omega, int64_t ldo, int64_t k,
+                        void* Y, int y_dtype, int64_t ldy, int beta, void* workspace,
+                        size_t workspace_bytes, void* stream) {
+    if (n > 0 && m > 0 && k > 0 && (Omega == nullptr || ldo < k)) return SK_EINVAL;
+    return gen_matmul_impl(A, a_dtype, m, n, lda, a_scales, 0, 0, 0, Omega, ldo < 1 ? 1 : ldo, k,
+                           Y, y_dtype, ldy, beta, workspace, workspace_bytes, stream);
+}
+
+int sketch_gen_matmul_reduce(const void* const* A_b, int64_t P, int a_dtype, int64_t m,
+                             const int64_t* n_b, const int64_t* lda_b, const int64_t* row0_b,
+                             const float* const* a_scales_b, uint64_t seed, int64_t omega_col0,
+                             int64_t k, void* Y, int y_dtype, int64_t ldy, int beta,
+                             void* workspace, size_t workspace_bytes, void* stream) {
+    int st = check_common(a_dtype, m, k, omega_col0, Y, y_dtype, ldy, beta);
+    if (st != SK_OK) return st;
+    if (P < 1 || P > sk::kMaxBlocks) return SK_EINVAL;
+    if (A_b == nullptr || n_b == nullptr || lda_b == nullptr || row0_b == nullptr)
+        return SK_EINVAL;
+    int64_t n_total = 0;
+    for (int64_t b = 0; b < P; ++b) {
+        const float* sc = a_scales_b ? a_scales_b[b] : nullptr;
+        st = check_block(A_b[b], a_dtype, m, n_b[b], lda_b[b], row0_b[b], sc);
+        if (st != SK_OK) return st;
+        n_total += n_b[b];
+    }
+    if (m == 0 || k == 0) return SK_OK;
+    sk::GemmLaunch g{};
+    g.adtype = a_dtype;
+    g.m = m;
+    g.P = (int)P;
+    for (int64_t b = 0; b < P; ++b)
+        g.blk[b] = sk::BlockDesc{A_b[b], n_b[b], lda_b[b], row0_b[b],
+                                 a_scales_b ? a_scales_b[b] : nullptr};
+    g.k = k;
+    g.col0 = (uint32_t)omega_col0;
+    g.seed = seed;
+    g.omega = nullptr;
+    g.Y = Y;
+    g.y_f64 = (y_dtype == SK_Y_F64);
+    g.ldy = ldy;
+    g.beta = beta;
+    g.workspace = workspace;
+    g.workspace_bytes = workspace_bytes;
+    g.stream = static_cast<hipStream_t>(stream);
+    const int64_t S = sk::count_strips(g, (int)(k < sk::kColGroup ? k : sk::kColGroup));
+    st = check_workspace(n_total > 0 ? sk::gemm_workspace_bytes(m, S, k) : 0, workspace,
+                         workspace_bytes);
+    if (st != SK_OK) return st;
+    return run_product(g, n_total);
+}
+
+int sketch_gen_omega(uint64_t seed, int64_t row0, int64_t n, int64_t col0, int64_t k,
+                     float* Omega, int64_t ldo, void* stream) {
+    if (n < 0 || k < 0 || row0 < 0 || row0 > kMaxRow - n || col0 < 0 || col0 + k > kMaxCol)
+        return SK_EINVAL;
+    if (n == 0 || k == 0) return SK_OK;
+    if (Omega == nullptr || ldo < k) return SK_EINVAL;
+    if (((uintptr_t)Omega & 3u) != 0) return SK_EALIGN;
+    return from_hip(sk::launch_gen_omega(seed, row0, n, col0, k, Omega, ldo,
+                                         static_cast<hipStream_t>(stream)));
+}
+
+int sketch_philox_raw(const uint32_t* ctr, uint64_t seed, uint32_t* out, int64_t N,
+                      void* stream) {
+    if (N < 0) return SK_EINVAL;
+    if (N == 0) return SK_OK;
+    if (ctr == nullptr || out == nullptr) return SK_EINVAL;
+    if (!aligned16(ctr) || !aligned16(out)) return SK_EALIGN;
+    return from_hip(sk::launch_philox_raw(ctr, seed, out, N, static_cast<hipStream_t>(stream)));
+}
+
+int sketch_quantize(const float* A, int64_t m, int64_t n, int64_t lda, int dst_dtype, void* Aq,
+                    int64_t ldq, float* scales, void* stream) {
+    if (dst_dtype != SK_A_BF16 && dst_dtype != SK_A_FP8_E4M3) return SK_EDTYPE;
+    if (m < 0 || n < 0) return SK_EINVAL;
+    if (m == 0) return SK_OK;
+    if (dst_dtype == SK_A_FP8_E4M3 && scales == nullptr) return SK_EINVAL;
+    if (scales && ((uintptr_t)scales & 3u)) return SK_EALIGN;
+    if (n > 0) {
+        if (A == nullptr || Aq == nullptr || lda < n || ldq < n) return SK_EINVAL;
+        if (((uintptr_t)A & 3u) != 0) return SK_EALIGN;
+        if (!aligned16(Aq) || (ldq * elem_size(dst_dtype)) % 16 != 0) return SK_EALIGN;
+    }
+    if (m > kMaxGridY) return SK_EUNSUPPORTED;
+    return from_hip(sk::launch_quantize(A, m, n, lda, dst_dtype, Aq, ldq, scales,
+                                        static_cast<hipStream_t>(stream)));
+}
+
+}  // extern "C"

@@ -1,0 +1,433 @@
+// Streaming kernel for Y = A * Omega(seed) on gfx950 (small sketch width).
+//
+// The local product of Alg. 1 (GenRandom + local multiplication) and, for a
+// contraction split, the sum of the partial products (the Reduce-Scatter of
+// Alg. 1, done on the device), in one launch.
+//
+// Work decomposition (one workgroup = one tile):
+//   * a strip of C consecutive columns of one A block (C = strip_width(kg))
+//     times a range of R rows, for a group of kg <= 16 Omega columns;
+//   * the workgroup first builds its C x kg slice of Omega in LDS (generated
+//     from the seed, or copied from an explicit Omega for the stored-operand
+//     variant), so Omega never exists in HBM on the generated path;
+//   * each wave then streams 16 rows at a time: 16 lanes per row, each lane
+//     loading 16 contiguous bytes of A per step (a 256-byte coalesced row
+//     segment), multiplying by the matching Omega values from LDS with FP32
+//     FMAs into per-lane accumulators;
+//   * the 16 lanes of a row are summed by a fixed DPP butterfly, giving the
+//     FP32 partial of (row, strip, column); partials go to the workspace;
+//   * the last workgroup to finish a row block (device-scope counter) sums
+//     the partials of all strips of that row block in FP64, in strip order,
+//     adds beta * Y, rounds once and writes Y.
+// The summation order depends only on the strip boundaries, never on m, R or
+// the grid, so results are bitwise reproducible and layout independent.
+#include "sk_device.hpp"
+#include "sk_internal.hpp"
+
+#pragma clang fp contract(off)
+
+namespace sk {
+namespace {
+
+constexpr int kLanesPerRow = 16;  // lanes sharing one row segment
+constexpr int kRowGroups = 4;     // row groups per wave pass (4 rows each)
+
+struct KArgs {
+    int64_t m;
+    int64_t k;
+    int64_t ldy;
+    int64_t ldo;
+    const float* omega;
+    void* Y;
+    float* partials;
+    uint32_t* counters;
+    uint32_t key0, key1;
+    uint32_t col0;
+    int P;
+    int S_total;
+    int rows_per_wg;
+    int num_rb;
+    int y_f64;
+    int beta;
+    BlockDesc blk[kMaxBlocks];
+};
+
+template <int ADT>
+struct Elem;
+template <>
+struct Elem<0> {
+    static constexpr int size = 4;
+};
+template <>
+struct Elem<1> {
+    static constexpr int size = 2;
+};
+template <>
+struct Elem<2> {
+    static constexpr int size = 1;
+};
+
+// 16 raw bytes of A -> EPL floats.
+template <int ADT>
+__device__ __forceinline__ void unpack16(const uint4 raw, float* out) {
+    if constexpr (ADT == 0) {
+        out[0] = __uint_as_float(raw.x);
+        out[1] = __uint_as_float(raw.y);
+        out[2] = __uint_as_float(raw.z);
+        out[3] = __uint_as_float(raw.w);
+    } else if constexpr (ADT == 1) {
+        const uint32_t w[4] = {raw.x, raw.y, raw.z, raw.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            out[2 * i] = __uint_as_float(w[i] << 16);
+            out[2 * i + 1] = __uint_as_float(w[i] & 0xFFFF0000u);
+        }
+    } else {
+        const uint32_t w[4] = {raw.x, raw.y, raw.z, raw.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[i], false);
+            const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[i], true);
+            out[4 * i + 0] = lo[0];
+            out[4 * i + 1] = lo[1];
+            out[4 * i + 2] = hi[0];
+            out[4 * i + 3] = hi[1];
+        }
+    }
+}
+
+// Load up to 16 bytes at p of which only `nvalid` elements exist; the rest
+// read as zero.  Used for the ragged last step of a strip.
+template <int ADT>
+__device__ __forceinline__ uint4 load_tail(const unsigned char* p, int nvalid) {
+    uint32_t w[4] = {0u, 0u, 0u, 0u};
+    constexpr int es = Elem<ADT>::size;
+    for (int e = 0; e < 16 / es; ++e) {
+        if (e < nvalid) {
+            uint32_t v;
+            if constexpr (es == 4) v = *reinterpret_cast<const uint32_t*>(p + 4 * e);
+            else if constexpr (es == 2) v = *reinterpret_cast<const uint16_t*>(p + 2 * e);
+            else v = p[e];
+            const int byte = e * es;
+            w[byte >> 2] |= v << (8 * (byte & 3));
+        }
+    }
+    return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+// Sum over the 16 lanes of a DPP row with a fixed butterfly; every lane of
+// the row receives the same bits.
+__device__ __forceinline__ float row16_sum(float v) {
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false));
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, false));
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, false));
+    return v;
+}
+
+template <int K, int ADT, bool GEN>
+__global__ __launch_bounds__(kWgThreads) void k_gemm_stream(const KArgs args) {
+    constexpr int es = Elem<ADT>::size;
+    constexpr int EPL = 16 / es;                 // elements per lane step
+    constexpr int C = strip_width(K);            // columns per strip
+    constexpr int STEP = kLanesPerRow * EPL;     // columns per wave step
+    constexpr int T = C / STEP;                  // steps per full strip
+    static_assert(C % STEP == 0, "strip must hold whole steps");
+    __shared__ float om[K][C];
+    __shared__ uint32_t s_last;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int sig = lane & (kLanesPerRow - 1);
+    const int rho = lane >> 4;
+
+    // ---- which block / strip / row block / column group -----------------
+    int strip = blockIdx.x;
+    int b = 0;
+    int64_t strip_in_block = strip;
+    for (; b < args.P; ++b) {
+        const int64_t sb = (args.blk[b].n + C - 1) / C;
+        if (strip_in_block < sb) break;
+        strip_in_block -= sb;
+    }
+    const BlockDesc blk = args.blk[b];
+    const int rb = blockIdx.y;
+    const int cg = blockIdx.z;
+    const int c_base = cg * kColGroup;
+    const int kg = (int)min<int64_t>(kColGroup, args.k - c_base);
+    const int64_t col_begin = strip_in_block * C;   // first A column of the strip
+    const int w = (int)min<int64_t>(C, blk.n - col_begin);
+    const int64_t row_begin = (int64_t)rb * args.rows_per_wg;
+    const int64_t row_end = min<int64_t>(row_begin + args.rows_per_wg, args.m);
+
+    // ---- Omega slice for this strip -> LDS --------------------------------
+    if constexpr (GEN) {
+        const int64_t g0 = blk.row0 + col_begin;           // global Omega row of column 0
+        const int64_t q_lo = g0 >> 2;
+        const int64_t q_hi = (g0 + w - 1) >> 2;
+        const int nq = (int)(q_hi - q_lo + 1);
+        const int items = nq * kg;
+        const bool aligned = (g0 & 3) == 0;
+        for (int it = tid; it < items; it += kWgThreads) {
+            const int qi = it / kg;
+            const int c = it - qi * kg;
+            const float4 z = omega4((uint64_t)(q_lo + qi), args.col0 + (uint32_t)(c_base + c),
+                                    args.key0, args.key1);
+            const int64_t p0 = 4 * (q_lo + qi) - g0;       // local column of z.x
+            if (aligned && p0 + 3 < w) {
+                *reinterpret_cast<float4*>(&om[c][p0]) = z;
+            } else {
+                const float zz[4] = {z.x, z.y, z.z, z.w};
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int64_t p = p0 + t;
+                    if (p >= 0 && p < w) om[c][p] = zz[t];
+                }
+            }
+        }
+    } else {
+        for (int it = tid; it < w * kg; it += kWgThreads) {
+            const int jl = it / kg;
+            const int c = it - jl * kg;
+            om[c][jl] = args.omega[(col_begin + jl) * args.ldo + c_base + c];
+        }
+    }
+    // zero the unused part of the slice (ragged strip, unused columns)
+    for (int it = tid; it < K * C; it += kWgThreads) {
+        const int c = it / C;
+        const int jl = it - c * C;
+        if (c >= kg || jl >= w) om[c][jl] = 0.0f;
+    }
+    __syncthreads();
+
+    // ---- stream the rows ---------------------------------------------------
+    const unsigned char* Abase = static_cast<const unsigned char*>(blk.A);
+    const int64_t lda_bytes = blk.lda * es;
+    const bool full = (w == C);
+    const bool single = (args.S_total == 1);
+    const float* scales = blk.scales;
+
+    for (int64_t pb = row_begin + wave * 16; pb < row_end; pb += kRowQuantum) {
+        float acc[kRowGroups][K];
+#pragma unroll
+        for (int i = 0; i < kRowGroups; ++i)
+#pragma unroll
+            for (int c = 0; c < K; ++c) acc[i][c] = 0.0f;
+
+        const unsigned char* rp[kRowGroups];
+#pragma unroll
+        for (int i = 0; i < kRowGroups; ++i) {
+            const int64_t r = min<int64_t>(pb + 4 * i + rho, args.m - 1);
+            rp[i] = Abase + r * lda_bytes + (col_begin + sig * EPL) * es;
+        }
+
+        auto step = [&](const uint4* raw, int t) {
+            float a[kRowGroups][EPL];
+#pragma unroll
+            for (int i = 0; i < kRowGroups; ++i) unpack16<ADT>(raw[i], a[i]);
+            const int cl = t * STEP + sig * EPL;
+#pragma unroll
+            for (int c = 0; c < K; ++c) {
+                float wv[EPL];
+#pragma unroll
+                for (int v = 0; v < EPL / 4; ++v) {
+                    const float4 q = *reinterpret_cast<const float4*>(&om[c][cl + 4 * v]);
+                    wv[4 * v + 0] = q.x;
+                    wv[4 * v + 1] = q.y;
+                    wv[4 * v + 2] = q.z;
+                    wv[4 * v + 3] = q.w;
+                }
+#pragma unroll
+                for (int i = 0; i < kRowGroups; ++i)
+#pragma unroll
+                    for (int e = 0; e < EPL; ++e) acc[i][c] = __builtin_fmaf(a[i][e], wv[e], acc[i][c]);
+            }
+        };
+
+        if (full) {
+            uint4 cur[kRowGroups], nxt[kRowGroups];
+#pragma unroll
+            for (int i = 0; i < kRowGroups; ++i) cur[i] = *reinterpret_cast<const uint4*>(rp[i]);
+#pragma unroll
+            for (int t = 0; t < T; ++t) {
+                if (t + 1 < T) {
+#pragma unroll
+                    for (int i = 0; i < kRowGroups; ++i)
+                        nxt[i] = *reinterpret_cast<const uint4*>(rp[i] + (int64_t)(t + 1) * STEP * es);
+                }
+                step(cur, t);
+#pragma unroll
+                for (int i = 0; i < kRowGroups; ++i) cur[i] = nxt[i];
+            }
+        } else {
+            const int Tw = (w + STEP - 1) / STEP;
+            for (int t = 0; t < Tw; ++t) {
+                const int cl = t * STEP + sig * EPL;
+                const int nvalid = w - cl;
+                uint4 raw[kRowGroups];
+#pragma unroll
+                for (int i = 0; i < kRowGroups; ++i) {
+                    const unsigned char* p = rp[i] + (int64_t)t * STEP * es;
+                    if (nvalid >= EPL) raw[i] = *reinterpret_cast<const uint4*>(p);
+                    else raw[i] = load_tail<ADT>(p, nvalid);
+                }
+                step(raw, t);
+            }
+        }
+
+        // ---- 16-lane sums and partial write ----------------------------------
+#pragma unroll
+        for (int i = 0; i < kRowGroups; ++i) {
+            float mine = 0.0f;
+#pragma unroll
+            for (int c = 0; c < K; ++c) {
+                const float s = row16_sum(acc[i][c]);
+                if (sig == c) mine = s;
+            }
+            const int64_t r = pb + 4 * i + rho;
+            if (r < row_end && sig < kg) {
+                if (scales) mine *= scales[r >> 7];
+                if (single) {
+                    double y = (double)mine;
+                    if (args.y_f64) {
+                        double* Yp = static_cast<double*>(args.Y) + r * args.ldy + c_base + sig;
+                        if (args.beta) y += *Yp;
+                        *Yp = y;
+                    } else {
+                        float* Yp = static_cast<float*>(args.Y) + r * args.ldy + c_base + sig;
+                        if (args.beta) y += (double)*Yp;
+                        *Yp = (float)y;
+                    }
+                } else {
+                    args.partials[((int64_t)strip * args.m + r) * args.k + c_base + sig] = mine;
+                }
+            }
+        }
+    }
+    if (single) return;
+
+    // ---- last workgroup of the row block sums the strips in FP64 ------------
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t* ctr = args.counters + (int64_t)cg * args.num_rb + rb;
+        const uint32_t old = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_ACQ_REL,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t last = (old == (uint32_t)(args.S_total - 1)) ? 1u : 0u;
+        if (last) __hip_atomic_store(ctr, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_last = last;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    const int64_t nrow = row_end - row_begin;
+    for (int64_t o = tid; o < nrow * kg; o += kWgThreads) {
+        const int64_t r = row_begin + o / kg;
+        const int c = c_base + (int)(o % kg);
+        double y = 0.0;
+        const float* p = args.partials + r * args.k + c;
+        const int64_t sstride = args.m * args.k;
+        for (int s = 0; s < args.S_total; ++s) y += (double)p[(int64_t)s * sstride];
+        if (args.y_f64) {
+            double* Yp = static_cast<double*>(args.Y) + r * args.ldy + c;
+            if (args.beta) y = *Yp + y;
+            *Yp = y;
+        } else {
+            float* Yp = static_cast<float*>(args.Y) + r * args.ldy + c;
+            if (args.beta) y = (double)*Yp + y;
+            *Yp = (float)y;
+        }
+    }
+}
+
+template <int K, int ADT, bool GEN>
+hipError_t launch_k(const KArgs& a, dim3 grid, hipStream_t s) {
+    hipLaunchKernelGGL((k_gemm_stream<K, ADT, GEN>), grid, dim3(kWgThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int ADT, bool GEN>
+hipError_t dispatch_k(int kc, const KArgs& a, dim3 grid, hipStream_t s) {
+    switch (kc) {
+    case 1: return launch_k<1, ADT, GEN>(a, grid, s);
+    case 2: return launch_k<2, ADT, GEN>(a, grid, s);
+    case 3: return launch_k<3, ADT, GEN>(a, grid, s);
+    case 4: return launch_k<4, ADT, GEN>(a, grid, s);
+    case 5: return launch_k<5, ADT, GEN>(a, grid, s);
+    case 6: return launch_k<6, ADT, GEN>(a, grid, s);
+    case 8: return launch_k<8, ADT, GEN>(a, grid, s);
+    case 12: return launch_k<12, ADT, GEN>(a, grid, s);
+    default: return launch_k<16, ADT, GEN>(a, grid, s);
+    }
+}
+
+int wg_target() {
+    static int t = [] {
+        const char* e = getenv("SKETCH_WG_TARGET");
+        int v = e ? atoi(e) : 0;
+        return v > 0 ? v : 1024;
+    }();
+    return t;
+}
+
+}  // namespace
+
+int64_t count_strips(const GemmLaunch& g, int kg) {
+    const int C = strip_width(k_class(kg));
+    int64_t s = 0;
+    for (int b = 0; b < g.P; ++b) s += (g.blk[b].n + C - 1) / C;
+    return s;
+}
+
+size_t gemm_workspace_bytes(int64_t m, int64_t strips, int64_t k) {
+    if (strips <= 1) return 0;
+    const size_t part = (size_t)strips * (size_t)m * (size_t)k * sizeof(float);
+    const size_t part_al = (part + 255) & ~(size_t)255;
+    const int64_t ncg = (k + kColGroup - 1) / kColGroup;
+    const int64_t nrb = (m + kRowQuantum - 1) / kRowQuantum;
+    return part_al + (size_t)(ncg * nrb) * sizeof(uint32_t);
+}
+
+hipError_t launch_gemm_stream(const GemmLaunch& g) {
+    const int64_t ncg = (g.k + kColGroup - 1) / kColGroup;
+    const int kg0 = (int)std::min<int64_t>(g.k, kColGroup);
+    const int kc = k_class(kg0);
+    const int64_t S = count_strips(g, kg0);
+    KArgs a{};
+    a.m = g.m;
+    a.k = g.k;
+    a.ldy = g.ldy;
+    a.ldo = g.ldo;
+    a.omega = g.omega;
+    a.Y = g.Y;
+    a.key0 = (uint32_t)g.seed;
+    a.key1 = (uint32_t)(g.seed >> 32);
+    a.col0 = g.col0;
+    a.P = g.P;
+    a.S_total = (int)S;
+    a.y_f64 = g.y_f64;
+    a.beta = g.beta;
+    for (int b = 0; b < g.P; ++b) a.blk[b] = g.blk[b];
+    // rows per workgroup: a multiple of 64 giving about wg_target() workgroups
+    int64_t R = (g.m * S * ncg) / wg_target();
+    R = std::max<int64_t>(kRowQuantum, std::min<int64_t>(1024, (R / kRowQuantum) * kRowQuantum));
+    const int64_t nrb = (g.m + R - 1) / R;
+    a.rows_per_wg = (int)R;
+    a.num_rb = (int)nrb;
+    if (S > 1) {
+        const size_t part = (size_t)S * (size_t)g.m * (size_t)g.k * sizeof(float);
+        const size_t part_al = (part + 255) & ~(size_t)255;
+        a.partials = static_cast<float*>(g.workspace);
+        a.counters = reinterpret_cast<uint32_t*>(static_cast<char*>(g.workspace) + part_al);
+    }
+    dim3 grid((unsigned)S, (unsigned)nrb, (unsigned)ncg);
+    const bool gen = (g.omega == nullptr);
+    switch (g.adtype) {
+    case 0: return gen ? dispatch_k<0, true>(kc, a, grid, g.stream) : dispatch_k<0, false>(kc, a, grid, g.stream);
+    case 1: return gen ? dispatch_k<1, true>(kc, a, grid, g.stream) : dispatch_k<1, false>(kc, a, grid, g.stream);
+    default: return gen ? dispatch_k<2, true>(kc, a, grid, g.stream) : dispatch_k<2, false>(kc, a, grid, g.stream);
+    }
+}
+
+}  // namespace sk

@@ -1,0 +1,71 @@
+// Host-side interfaces between the C ABI layer and the kernel translation
+// units.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace sk {
+
+constexpr int kMaxBlocks = 64;     // contraction blocks per reduce call
+constexpr int kColGroup = 16;      // Omega columns handled by one workgroup
+constexpr int kWgThreads = 256;    // threads per workgroup of the streaming kernel
+constexpr int kRowQuantum = 64;    // rows per workgroup pass (4 waves x 16 rows)
+
+// Register-tile class (template K of the streaming kernel) for a group of
+// kg Omega columns.
+constexpr int k_class(int kg) { return kg <= 6 ? kg : kg <= 8 ? 8 : kg <= 12 ? 12 : 16; }
+
+// Strip width (columns of A per workgroup, and per FP32 partial sum).  A
+// function of the tile class only, so results never depend on m or on the
+// launch shape.
+constexpr int strip_width(int kclass) { return kclass <= 8 ? 1024 : 512; }
+
+// Strip width used for a sketch of width k (first column group).
+constexpr int64_t strip_width_for_k(int64_t k) {
+    return strip_width(k_class((int)(k < kColGroup ? k : kColGroup)));
+}
+
+struct BlockDesc {
+    const void* A;        // device pointer to the block's first element
+    int64_t n;            // columns of the block
+    int64_t lda;          // leading dimension (elements)
+    int64_t row0;         // global Omega row of the block's column 0
+    const float* scales;  // per-128-row scales or nullptr
+};
+
+struct GemmLaunch {
+    int adtype;               // 0 f32, 1 bf16, 2 fp8
+    int64_t m;
+    int P;
+    BlockDesc blk[kMaxBlocks];
+    int64_t k;
+    uint32_t col0;
+    uint64_t seed;
+    const float* omega;       // explicit Omega (n x k) or nullptr to generate
+    int64_t ldo;
+    void* Y;
+    int y_f64;
+    int64_t ldy;
+    int beta;
+    void* workspace;
+    size_t workspace_bytes;
+    hipStream_t stream;
+};
+
+// Number of FP32 strip partials for a set of blocks and a column-group size.
+int64_t count_strips(const GemmLaunch& g, int kg);
+size_t gemm_workspace_bytes(int64_t m, int64_t strips, int64_t k);
+
+hipError_t launch_gemm_stream(const GemmLaunch& g);
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+hipError_t launch_zero_matrix(void* Y, int f64, int64_t m, int64_t k, int64_t ldy, hipStream_t s);
+hipError_t launch_philox_raw(const uint32_t* ctr, uint64_t seed, uint32_t* out, int64_t N,
+                             hipStream_t s);
+hipError_t launch_gen_omega(uint64_t seed, int64_t row0, int64_t n, int64_t col0, int64_t k,
+                            float* Om, int64_t ldo, hipStream_t s);
+hipError_t launch_quantize(const float* A, int64_t m, int64_t n, int64_t lda, int dst, void* Aq,
+                           int64_t ldq, float* scales, hipStream_t s);
+
+}  // namespace sk

@@ -1,0 +1,206 @@
+// Auxiliary kernels: raw Philox stream export, explicit Omega fill (the
+// stored-operand alternative of Sec. 6.3), workspace zeroing, and the
+// low-precision storage of A (bf16 / fp8 e4m3 with per-128-row scales).
+#include "sk_device.hpp"
+#include "sk_internal.hpp"
+
+#pragma clang fp contract(off)
+
+namespace sk {
+namespace {
+
+__global__ void k_philox_raw(const uint4* ctr, uint32_t k0, uint32_t k1, uint4* out, int64_t N) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const uint4 c = ctr[i];
+    const Words4 r = philox4x32_10(Words4{c.x, c.y, c.z, c.w}, k0, k1);
+    out[i] = make_uint4(r.x, r.y, r.z, r.w);
+}
+
+// One thread per (Philox counter q, column c): writes Omega rows 4q..4q+3
+// that fall inside [row0, row0+n).
+__global__ void k_gen_omega(uint32_t k0, uint32_t k1, int64_t row0, int64_t n, int64_t col0,
+                            int64_t k, float* Om, int64_t ldo, int64_t q_lo, int64_t nq) {
+    const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (it >= nq * k) return;
+    const int64_t qi = it / k;
+    const int64_t c = it - qi * k;
+    const int64_t q = q_lo + qi;
+    const float4 z = omega4((uint64_t)q, (uint32_t)(col0 + c), k0, k1);
+    const float zz[4] = {z.x, z.y, z.z, z.w};
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int64_t j = 4 * q + t - row0;
+        if (j >= 0 && j < n) Om[j * ldo + c] = zz[t];
+    }
+}
+
+__global__ void k_zero(uint32_t* p, int64_t words) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+__global__ void k_zero_matrix(void* Y, int f64, int64_t m, int64_t k, int64_t ldy) {
+    const int64_t i = blockIdx.y;
+    for (int64_t c = threadIdx.x; c < k; c += blockDim.x) {
+        if (f64) static_cast<double*>(Y)[i * ldy + c] = 0.0;
+        else static_cast<float*>(Y)[i * ldy + c] = 0.0f;
+    }
+}
+
+__global__ void k_zero_bytes(unsigned char* p, int64_t bytes) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < bytes) p[i] = 0;
+}
+
+// bf16 = round-to-nearest-even of the upper half of the FP32 pattern.
+__global__ void k_to_bf16(const float* A, int64_t m, int64_t n, int64_t lda, uint16_t* Q,
+                          int64_t ldq) {
+    const int64_t i = blockIdx.y;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t u = __float_as_uint(A[i * lda + j]);
+        uint16_t h;
+        if ((u & 0x7FFFFFFFu) > 0x7F800000u) h = (uint16_t)((u >> 16) | 0x40u);
+        else h = (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+        Q[i * ldq + j] = h;
+    }
+}
+
+// max |A| of each 128-row block, as the FP32 bit pattern (monotone for
+// non-negative values), via device-scope atomic max.
+__global__ void k_amax_rows128(const float* A, int64_t m, int64_t n, int64_t lda, uint32_t* amax) {
+    const int64_t i = blockIdx.y;
+    uint32_t mx = 0u;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * blockDim.x)
+        mx = max(mx, __float_as_uint(A[i * lda + j]) & 0x7FFFFFFFu);
+    for (int off = 32; off > 0; off >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, off));
+    if ((threadIdx.x & 63) == 0) atomicMax(&amax[i >> 7], mx);
+}
+
+// amax bits -> power-of-two scale 2^E, the smallest with amax <= 448 * 2^E.
+__global__ void k_fp8_scales(uint32_t* s, int64_t nb) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    const uint32_t bits = s[b];
+    float scale = 1.0f;
+    if (bits != 0u) {
+        const float amax = __uint_as_float(bits);
+        int E = -150;
+        // 448 * 2^E grows by 2x per step; start below any FP32 value
+        float lim = __builtin_ldexpf(448.0f, E);
+        while (lim < amax) {
+            ++E;
+            lim = __builtin_ldexpf(448.0f, E);
+        }
+        scale = __builtin_ldexpf(1.0f, E);
+    }
+    reinterpret_cast<float*>(s)[b] = scale;
+}
+
+// E4M3FN code of x (|x| <= 448 after scaling), round to nearest even,
+// saturating at +-448, from the FP32 bit pattern.
+__device__ __forceinline__ uint8_t e4m3_code(float x) {
+    const uint32_t u = __float_as_uint(x);
+    const uint32_t sign = (u >> 24) & 0x80u;
+    const float a = fabsf(x);
+    if (!(a < 448.0f)) return (uint8_t)(sign | 0x7Eu);
+    if (a < 0x1p-6f) {
+        // subnormal grid, spacing 2^-9; code = M, and M = 8 is exactly 2^-6 (code 8)
+        const uint32_t M = (uint32_t)__builtin_rintf(a * 512.0f);
+        return (uint8_t)(sign | M);
+    }
+    const uint32_t ua = __float_as_uint(a);
+    int ue = (int)((ua >> 23) & 0xFFu) - 127;          // -6 .. 8
+    uint32_t mant = ua & 0x7FFFFFu;
+    uint32_t m3 = mant >> 20;
+    const uint32_t rem = mant & 0xFFFFFu;
+    if (rem > 0x80000u || (rem == 0x80000u && (m3 & 1u))) ++m3;
+    if (m3 == 8u) { m3 = 0u; ++ue; }
+    uint32_t code = ((uint32_t)(ue + 7) << 3) | m3;
+    if (code > 0x7Eu) code = 0x7Eu;
+    return (uint8_t)(sign | code);
+}
+
+__global__ void k_to_fp8(const float* A, int64_t m, int64_t n, int64_t lda, const float* scales,
+                         uint8_t* Q, int64_t ldq) {
+    const int64_t i = blockIdx.y;
+    const float inv = 1.0f / scales[i >> 7];   // exact: scales are powers of two
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * blockDim.x)
+        Q[i * ldq + j] = e4m3_code(A[i * lda + j] * inv);
+}
+
+}  // namespace
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
+    if (bytes == 0) return hipSuccess;
+    const int64_t words = (int64_t)(bytes / 4);
+    if (words) {
+        const int64_t blocks = std::min<int64_t>((words + 255) / 256, 4096);
+        hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, s,
+                           static_cast<uint32_t*>(p), words);
+    }
+    const int64_t tail = (int64_t)(bytes - 4 * (size_t)words);
+    if (tail)
+        hipLaunchKernelGGL(k_zero_bytes, dim3(1), dim3(64), 0, s,
+                           static_cast<unsigned char*>(p) + 4 * words, tail);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_matrix(void* Y, int f64, int64_t m, int64_t k, int64_t ldy,
+                              hipStream_t s) {
+    if (m == 0 || k == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_matrix, dim3(1, (unsigned)m), dim3(64), 0, s, Y, f64, m, k, ldy);
+    return hipGetLastError();
+}
+
+hipError_t launch_philox_raw(const uint32_t* ctr, uint64_t seed, uint32_t* out, int64_t N,
+                             hipStream_t s) {
+    if (N == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_philox_raw, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s,
+                       reinterpret_cast<const uint4*>(ctr), (uint32_t)seed,
+                       (uint32_t)(seed >> 32), reinterpret_cast<uint4*>(out), N);
+    return hipGetLastError();
+}
+
+hipError_t launch_gen_omega(uint64_t seed, int64_t row0, int64_t n, int64_t col0, int64_t k,
+                            float* Om, int64_t ldo, hipStream_t s) {
+    if (n == 0 || k == 0) return hipSuccess;
+    const int64_t q_lo = row0 >> 2;
+    const int64_t nq = ((row0 + n - 1) >> 2) - q_lo + 1;
+    const int64_t items = nq * k;
+    hipLaunchKernelGGL(k_gen_omega, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, s,
+                       (uint32_t)seed, (uint32_t)(seed >> 32), row0, n, col0, k, Om, ldo, q_lo,
+                       nq);
+    return hipGetLastError();
+}
+
+hipError_t launch_quantize(const float* A, int64_t m, int64_t n, int64_t lda, int dst, void* Aq,
+                           int64_t ldq, float* scales, hipStream_t s) {
+    if (m == 0) return hipSuccess;
+    const unsigned gx = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 64));
+    dim3 grid(gx, (unsigned)m);
+    if (dst == 1) {
+        if (n == 0) return hipSuccess;
+        hipLaunchKernelGGL(k_to_bf16, grid, dim3(256), 0, s, A, m, n, lda,
+                           static_cast<uint16_t*>(Aq), ldq);
+        return hipGetLastError();
+    }
+    const int64_t nb = (m + 127) / 128;
+    hipError_t e = launch_zero(scales, (size_t)nb * sizeof(float), s);
+    if (e != hipSuccess) return e;
+    if (n > 0)
+        hipLaunchKernelGGL(k_amax_rows128, grid, dim3(256), 0, s, A, m, n, lda,
+                           reinterpret_cast<uint32_t*>(scales));
+    hipLaunchKernelGGL(k_fp8_scales, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s,
+                       reinterpret_cast<uint32_t*>(scales), nb);
+    if (n > 0)
+        hipLaunchKernelGGL(k_to_fp8, grid, dim3(256), 0, s, A, m, n, lda, scales,
+                           static_cast<uint8_t*>(Aq), ldq);
+    return hipGetLastError();
+}
+
+}  // namespace sk

@@ -1,0 +1,154 @@
+"""C ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, and rejects bad arguments on the host before enqueuing work.
+
+Only invalid argument combinations are passed here (with placeholder
+addresses that are never dereferenced): every such call returns before any
+HIP call is made.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sketch.h")
+
+import paper_2603_20966_amd as sk  # noqa: E402
+
+F32, BF16, FP8 = 0, 1, 2
+YF32, YF64 = 0, 1
+OK, EINVAL, EDTYPE, EALIGN, EWS, EHIP, ENOMEM, EUNSUP = 0, -1, -2, -3, -4, -5, -6, -7
+PA = 0x10000      # 16-byte aligned placeholder addresses (never dereferenced)
+PB = 0x20000
+PW = 0x30000
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sketch_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_symbols_exported():
+    L = sk.lib()
+    names = declared_functions()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(L, name), name
+    # and nothing exported under the ABI prefix that the header does not declare
+    out = os.popen(f"nm -D --defined-only {sk.LIB_PATH}").read()
+    exported = set(re.findall(r" T (sketch_[a-z_0-9]+)$", out, flags=re.M))
+    assert exported == set(names)
+
+
+def test_version_and_status_strings():
+    assert sk.sketch_abi_version() == 1
+    for st in range(-9, 1):
+        assert sk.sketch_status_string(st) != "unknown status"
+    assert sk.sketch_status_string(-100) == "unknown status"
+
+
+def gm(A=PA, adt=F32, m=64, n=1024, lda=1024, scales=None, seed=1, row0=0, col0=0, k=5, Y=PB,
+       ydt=YF32, ldy=5, beta=0, ws=PW, wsb=1 << 30, stream=None):
+    return sk.lib().sketch_gen_matmul(A, adt, m, n, lda, scales, seed, row0, col0, k, Y, ydt, ldy,
+                                      beta, ws, wsb, stream)
+
+
+@pytest.mark.parametrize("kw,expect", [
+    (dict(adt=3), EDTYPE), (dict(adt=-1), EDTYPE), (dict(ydt=2), EDTYPE),
+    (dict(m=-1), EINVAL), (dict(n=-1), EINVAL), (dict(k=-1), EINVAL), (dict(k=257), EINVAL),
+    (dict(beta=2), EINVAL), (dict(Y=None), EINVAL), (dict(ldy=4), EINVAL),
+    (dict(A=None), EINVAL), (dict(lda=1000), EINVAL), (dict(row0=-1), EINVAL),
+    (dict(row0=(1 << 62) - 100), EINVAL), (dict(col0=-1), EINVAL),
+    (dict(col0=(1 << 32) - 4), EINVAL),
+    (dict(A=PA + 4), EALIGN), (dict(lda=1025, n=1025), EALIGN), (dict(Y=PB + 2), EALIGN),
+    (dict(ydt=YF64, Y=PB + 4, ldy=5), EALIGN),
+    (dict(adt=FP8, lda=1024), EINVAL),                  # fp8 needs scales
+    (dict(adt=BF16, lda=1028, n=1028), EALIGN),          # 1028*2 % 16 != 0
+    (dict(ws=None), EWS), (dict(wsb=16), EWS), (dict(ws=PW + 8), EALIGN),
+    (dict(m=70_000_000), EUNSUP),
+])
+def test_gen_matmul_rejects(kw, expect):
+    args = dict(n=4096, lda=4096)
+    args.update(kw)
+    assert gm(**args) == expect
+
+
+def test_noop_shapes_return_ok_without_launch():
+    # m == 0 or k == 0 is a no-op: nothing is enqueued, pointers are not used
+    assert gm(m=0, Y=None, A=None) == OK
+    assert gm(k=0, Y=None, ldy=0) == OK
+
+
+def test_reduce_rejects():
+    L = sk.lib()
+    P = 2
+    A = (ctypes.c_void_p * P)(PA, PA + 4096 * 4)
+    nb = (ctypes.c_int64 * P)(4096, 4096)
+    ld = (ctypes.c_int64 * P)(8192, 8192)
+    r0 = (ctypes.c_int64 * P)(0, 4096)
+
+    def call(P=P, A=A, adt=F32, m=64, nb=nb, ld=ld, r0=r0, sc=None, k=5, Y=PB, ldy=5, ws=PW,
+             wsb=1 << 30):
+        return L.sketch_gen_matmul_reduce(A, P, adt, m, nb, ld, r0, sc, 1, 0, k, Y, YF32, ldy, 0,
+                                          ws, wsb, None)
+
+    assert call(P=0) == EINVAL
+    assert call(P=65) == EINVAL
+    assert call(A=None) == EINVAL
+    assert call(nb=None) == EINVAL
+    bad_ld = (ctypes.c_int64 * P)(8192, 4000)
+    assert call(ld=bad_ld) == EINVAL
+    bad_al = (ctypes.c_void_p * P)(PA, PA + 4)
+    assert call(A=bad_al) == EALIGN
+    assert call(ws=None) == EWS
+    assert call(adt=FP8) == EINVAL       # fp8 without scales
+    bad_r0 = (ctypes.c_int64 * P)(0, -5)
+    assert call(r0=bad_r0) == EINVAL
+
+
+def test_other_entry_points_reject():
+    L = sk.lib()
+    assert L.sketch_gen_omega(1, 0, 10, 0, 5, None, 5, None) == EINVAL
+    assert L.sketch_gen_omega(1, 0, 10, 0, 5, PA, 4, None) == EINVAL
+    assert L.sketch_gen_omega(1, -1, 10, 0, 5, PA, 5, None) == EINVAL
+    assert L.sketch_gen_omega(1, 0, 10, 0, 5, PA + 2, 5, None) == EALIGN
+    assert L.sketch_gen_omega(1, 0, 0, 0, 5, None, 5, None) == OK
+    assert L.sketch_philox_raw(PA, 1, PB, -1, None) == EINVAL
+    assert L.sketch_philox_raw(PA + 4, 1, PB, 8, None) == EALIGN
+    assert L.sketch_philox_raw(None, 1, PB, 8, None) == EINVAL
+    assert L.sketch_philox_raw(PA, 1, PB, 0, None) == OK
+    assert L.sketch_quantize(PA, 10, 10, 10, 0, PB, 16, PW, None) == EDTYPE
+    assert L.sketch_quantize(PA, 10, 10, 10, FP8, PB, 16, None, None) == EINVAL
+    assert L.sketch_quantize(PA, 10, 10, 10, BF16, PB, 12, None, None) == EALIGN
+    assert L.sketch_quantize(PA, 10, 10, 9, BF16, PB, 16, None, None) == EINVAL
+    assert L.sketch_matmul_omega(PA, F32, 64, 1024, 1024, None, None, 5, 5, PB, YF32, 5, 0, PW,
+                                 1 << 30, None) == EINVAL
+    assert L.sketch_matmul_omega(PA, F32, 64, 1024, 1024, None, PW, 4, 5, PB, YF32, 5, 0, PW,
+                                 1 << 30, None) == EINVAL
+    assert L.sketch_workspace_init(None, 16, None) == EINVAL
+    assert L.sketch_workspace_init(None, 0, None) == OK
+
+
+def test_workspace_size_rules():
+    ws = sk.sketch_workspace_size
+    assert ws(0, F32, 4096, 1024, 5, 1) == 0          # one strip: written directly, no partials
+    a = ws(0, F32, 4096, 32768, 5, 1)
+    assert a >= 32 * 4096 * 5 * 4                       # 32 strips of 1024 columns
+    b = ws(1, F32, 32768, 32768, 5, 8)
+    assert b >= (32 + 8) * 32768 * 5 * 4                # bound valid for any 8-way split
+    assert ws(2, F32, 1, 1, 1, 1) == 0 and ws(0, 5, 1, 1, 1, 1) == 0 and ws(1, F32, 1, 1, 1, 0) == 0
+    assert ws(0, F32, 100, 5000, 300, 1) == 0           # k > 256 is invalid
+    # a wider sketch uses narrower strips
+    assert ws(0, F32, 4096, 32768, 16, 1) >= 64 * 4096 * 16 * 4
+
+
+def test_python_binding_requires_library(monkeypatch, tmp_path):
+    import importlib
+
+    mod = importlib.import_module("paper_2603_20966_amd")
+    monkeypatch.setattr(mod, "_lib", None)
+    monkeypatch.setattr(mod, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError, match="no CPU fallback"):
+        mod.lib()
