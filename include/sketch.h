@@ -93,8 +93,10 @@ size_t sketch_workspace_size(int op, int a_dtype, int64_t m, int64_t n, int64_t 
 
 /* Prepare a workspace for first use: zero its `bytes` bytes on `stream`.
  * A workspace must be prepared once after allocation (or be allocated zeroed);
- * every call that completes leaves it prepared again.  One workspace serves
- * one call at a time: calls that overlap in time need separate workspaces. */
+ * its first 256 KiB hold completion counters that every call that completes
+ * leaves at zero again, so a prepared workspace serves any later call whose
+ * size fits.  One workspace serves one call at a time: calls that overlap in
+ * time need separate workspaces. */
 int sketch_workspace_init(void* workspace, size_t bytes, void* stream);
 
 /*

@@ -95,12 +95,32 @@ __device__ __forceinline__ void cos_sin_2pi_u24(uint32_t mo, float& c_out, float
     s_out = (quad >= 2u) ? -bb : bb;
 }
 
+// Correctly rounded square root of a positive normal x.  The hardware
+// estimate s is within one ulp of sqrt(x), so the rounded root is s or one of
+// its neighbours s- and s+.  x - s+- * s is formed exactly by an fma before
+// its single rounding, so its sign is exact: x <= s- * s means sqrt(x) lies
+// below the midpoint of s- and s (the product differs from the squared
+// midpoint by a quarter ulp^2, finer than the spacing of x and of the
+// products themselves), and x > s+ * s means it lies above the midpoint of s
+// and s+.
+__device__ __forceinline__ float sqrt_rn(float x) {
+    const float s = __builtin_amdgcn_sqrtf(x);
+    const float s_dn = __uint_as_float(__float_as_uint(s) - 1u);
+    const float s_up = __uint_as_float(__float_as_uint(s) + 1u);
+    const float r_dn = __builtin_fmaf(-s_dn, s, x);
+    const float r_up = __builtin_fmaf(-s_up, s, x);
+    float r = s;
+    if (r_dn <= 0.0f) r = s_dn;
+    if (r_up > 0.0f) r = s_up;
+    return r;
+}
+
 // Box-Muller on one word pair: (rho cos theta, rho sin theta) with
 // rho = sqrt(-2 ln u_even), theta = 2 pi u_odd.
 __device__ __forceinline__ void box_muller(uint32_t r_even, uint32_t r_odd, float& z_cos,
                                            float& z_sin) {
     const float L = log_u24(odd24(r_even));
-    const float rho = __fsqrt_rn(-2.0f * L);
+    const float rho = sqrt_rn(-2.0f * L);  // -2L in [2^-23.9, 33.3]: normal
     float c, s;
     cos_sin_2pi_u24(odd24(r_odd), c, s);
     z_cos = rho * c;

@@ -382,11 +382,7 @@ int64_t count_strips(const GemmLaunch& g, int kg) {
 
 size_t gemm_workspace_bytes(int64_t m, int64_t strips, int64_t k) {
     if (strips <= 1) return 0;
-    const size_t part = (size_t)strips * (size_t)m * (size_t)k * sizeof(float);
-    const size_t part_al = (part + 255) & ~(size_t)255;
-    const int64_t ncg = (k + kColGroup - 1) / kColGroup;
-    const int64_t nrb = (m + kRowQuantum - 1) / kRowQuantum;
-    return part_al + (size_t)(ncg * nrb) * sizeof(uint32_t);
+    return kCounterBytes + (size_t)strips * (size_t)m * (size_t)k * sizeof(float);
 }
 
 hipError_t launch_gemm_stream(const GemmLaunch& g) {
@@ -412,14 +408,13 @@ hipError_t launch_gemm_stream(const GemmLaunch& g) {
     // rows per workgroup: a multiple of 64 giving about wg_target() workgroups
     int64_t R = (g.m * S * ncg) / wg_target();
     R = std::max<int64_t>(kRowQuantum, std::min<int64_t>(1024, (R / kRowQuantum) * kRowQuantum));
+    while (ncg * ((g.m + R - 1) / R) > kMaxCounters) R *= 2;   // one counter per tile row
     const int64_t nrb = (g.m + R - 1) / R;
     a.rows_per_wg = (int)R;
     a.num_rb = (int)nrb;
     if (S > 1) {
-        const size_t part = (size_t)S * (size_t)g.m * (size_t)g.k * sizeof(float);
-        const size_t part_al = (part + 255) & ~(size_t)255;
-        a.partials = static_cast<float*>(g.workspace);
-        a.counters = reinterpret_cast<uint32_t*>(static_cast<char*>(g.workspace) + part_al);
+        a.counters = static_cast<uint32_t*>(g.workspace);
+        a.partials = reinterpret_cast<float*>(static_cast<char*>(g.workspace) + kCounterBytes);
     }
     dim3 grid((unsigned)S, (unsigned)nrb, (unsigned)ncg);
     const bool gen = (g.omega == nullptr);

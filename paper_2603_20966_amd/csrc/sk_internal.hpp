@@ -13,6 +13,11 @@ constexpr int kColGroup = 16;      // Omega columns handled by one workgroup
 constexpr int kWgThreads = 256;    // threads per workgroup of the streaming kernel
 constexpr int kRowQuantum = 64;    // rows per workgroup pass (4 waves x 16 rows)
 
+// Workspace layout: completion counters at a fixed place (the first
+// kCounterBytes, zero between calls), FP32 strip partials after them.
+constexpr int64_t kMaxCounters = 65536;
+constexpr size_t kCounterBytes = (size_t)kMaxCounters * 4;
+
 // Register-tile class (template K of the streaming kernel) for a group of
 // kg Omega columns.
 constexpr int k_class(int kg) { return kg <= 6 ? kg : kg <= 8 ? 8 : kg <= 12 ? 12 : 16; }

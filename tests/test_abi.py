@@ -135,7 +135,7 @@ def test_workspace_size_rules():
     ws = sk.sketch_workspace_size
     assert ws(0, F32, 4096, 1024, 5, 1) == 0          # one strip: written directly, no partials
     a = ws(0, F32, 4096, 32768, 5, 1)
-    assert a >= 32 * 4096 * 5 * 4                       # 32 strips of 1024 columns
+    assert a == 256 * 1024 + 32 * 4096 * 5 * 4          # counters + 32 strips of 1024 columns
     b = ws(1, F32, 32768, 32768, 5, 8)
     assert b >= (32 + 8) * 32768 * 5 * 4                # bound valid for any 8-way split
     assert ws(2, F32, 1, 1, 1, 1) == 0 and ws(0, 5, 1, 1, 1, 1) == 0 and ws(1, F32, 1, 1, 1, 0) == 0
