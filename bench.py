@@ -9,7 +9,8 @@ of the paper's 1D layouts emulated on one GPU:
 Each step streams A twice (8 GiB).  value = A bytes / wall time of the timed
 steps (GB/s).  The roofline object covers the streaming kernel: algorithmic
 bytes (A bytes; Omega is generated, never read) per launch / launch duration,
-measured with HIP events recorded on the launch stream.
+measured with HIP events that the library records on its launch stream just
+before and after that kernel (sketch_trace_events).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -34,33 +35,42 @@ def parse():
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-seconds", type=float, default=12.0,
-                   help="target duration of the oracle's timed sample")
+    p.add_argument("--cpu-seconds", type=float, default=10.0,
+                   help="minimum duration of the oracle's timed run")
     return p.parse_args()
 
 
-def cpu_baseline(A, k, seed, target_s):
-    """Time the CPU oracle on a bounded row sample of the same share workload."""
+def cpu_baseline(A, P, k, seed, target_s):
+    """Time the CPU oracle on the same step: the P row shares, then the P-block
+    column layout, over the same A (copied to the host beforehand, untimed).
+    The step is repeated until at least target_s seconds have elapsed."""
     import numpy as np
 
     import oracle
 
-    n = A.shape[1]
-    rows = 256
-    sample = A[:rows].cpu().numpy()
+    Ah = np.ascontiguousarray(A.cpu().numpy())
+    N = Ah.shape[0]
+    w = N // P
+
+    def step():
+        for i in range(P):
+            oracle.gen_matmul(Ah[i * w:(i + 1) * w], seed, 0, 0, k)
+        oracle.gen_matmul_reduce([Ah[:, b * w:(b + 1) * w] for b in range(P)],
+                                 [b * w for b in range(P)], seed, 0, k)
+
+    reps = 0
     t0 = time.perf_counter()
-    oracle.gen_matmul(sample, seed, 0, 0, k)
-    t_small = time.perf_counter() - t0
-    rows = int(min(A.shape[0], max(256, rows * target_s / max(t_small, 1e-3))))
-    rows = (rows // 256) * 256
-    sample = np.ascontiguousarray(A[:rows].cpu().numpy())
-    t0 = time.perf_counter()
-    oracle.gen_matmul(sample, seed, 0, 0, k)
-    dt = time.perf_counter() - t0
-    return {"value": rows * n * 4 / dt / 1e9, "unit": "GB/s", "cores": oracle.num_threads(),
+    while True:
+        step()
+        reps += 1
+        dt = time.perf_counter() - t0
+        if dt >= target_s or reps >= 200:
+            break
+    nbytes = 2 * Ah.nbytes * reps
+    return {"value": round(nbytes / dt / 1e9, 2), "unit": "GB/s", "cores": oracle.num_threads(),
             "kind": "oracle",
-            "sample": f"rows 0..{rows} of A x all {n} columns (row layout, k={k}, Omega generated "
-                      f"from the seed), {rows * n * 4 / 2**20:.0f} MiB, {dt:.2f} s"}
+            "sample": f"the whole step ({P} row shares + {P}-block column layout over the same "
+                      f"{N}x{N} A, k={k}) repeated {reps}x, {dt:.1f} s wall"}
 
 
 def main():
@@ -88,37 +98,38 @@ def main():
     share_bytes = w * N * 4
     red_bytes = N * N * 4
 
-    launches = []  # (start_event, end_event, bytes, kind)
+    # per-call phase events (streaming kernel, FP64 reduction), armed through
+    # sketch_trace_events and recorded by the library on the launch stream
+    def make_ev():
+        e = torch.cuda.Event(enable_timing=True)
+        e.record(stream)
+        return e
 
-    def step(record):
+    trace = [[tuple(make_ev() for _ in range(3)) for _ in range(P + 1)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+
+    def arm(ev):
+        sk.sketch_trace_events(ev[0].cuda_event, ev[1].cuda_event, ev[2].cuda_event)
+
+    def step(si):
         for i in range(P):
-            if record:
-                e0 = torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
+            if si is not None:
+                arm(trace[si][i])
             sk.sketch_gen_matmul(shares[i], seed, k, Y=Yrows[i * w:(i + 1) * w], stream=stream)
-            if record:
-                e1 = torch.cuda.Event(enable_timing=True)
-                e1.record(stream)
-                launches.append((e0, e1, share_bytes, "row"))
-        if record:
-            e0 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
+        if si is not None:
+            arm(trace[si][P])
         sk.sketch_gen_matmul_reduce(blocks, row0s, seed, k, Y=Yred, stream=stream)
-        if record:
-            e1 = torch.cuda.Event(enable_timing=True)
-            e1.record(stream)
-            launches.append((e0, e1, red_bytes, "col"))
 
     for _ in range(args.warmup):
-        step(False)
+        step(None)
     torch.cuda.synchronize()
     same = bool(torch.equal(Yrows, Yred))
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t_start.record(stream)
-    for _ in range(args.steps):
-        step(True)
+    for si in range(args.steps):
+        step(si)
     t_end.record(stream)
     torch.cuda.synchronize()
     total_ms = t_start.elapsed_time(t_end)
@@ -126,16 +137,22 @@ def main():
     step_bytes = P * share_bytes + red_bytes
     value = step_bytes * args.steps / (total_ms * 1e-3) / 1e9
 
-    dur = {"row": [], "col": []}
-    for e0, e1, nb, kind in launches:
-        dur[kind].append((e0.elapsed_time(e1), nb))
-    tot_b = sum(nb for v in dur.values() for _, nb in v)
-    tot_ms = sum(ms for v in dur.values() for ms, _ in v)
+    kern = {"row": [], "col": []}     # streaming-kernel durations (ms) per call
+    red = {"row": [], "col": []}      # FP64 reduction-kernel durations
+    for si in range(args.steps):
+        for i in range(P + 1):
+            e = trace[si][i]
+            kind = "row" if i < P else "col"
+            kern[kind].append(e[0].elapsed_time(e[1]))
+            red[kind].append(e[1].elapsed_time(e[2]))
+    nbytes = {"row": share_bytes, "col": red_bytes}
+    tot_b = sum(nbytes[kd] * len(v) for kd, v in kern.items())
+    tot_ms = sum(sum(v) for v in kern.values())
     achieved = tot_b / (tot_ms * 1e-3) / 1e9
-    n_launch = sum(len(v) for v in dur.values())
-    rate = {kd: sum(b for _, b in v) / (sum(ms for ms, _ in v) * 1e-3) / 1e9
-            for kd, v in dur.items()}
-    avg_us = {kd: 1e3 * sum(ms for ms, _ in v) / len(v) for kd, v in dur.items()}
+    n_launch = sum(len(v) for v in kern.values())
+    rate = {kd: nbytes[kd] * len(v) / (sum(v) * 1e-3) / 1e9 for kd, v in kern.items()}
+    avg_us = {kd: 1e3 * sum(v) / len(v) for kd, v in kern.items()}
+    red_us = {kd: 1e3 * sum(v) / len(v) for kd, v in red.items()}
 
     out = {
         "metric": METRIC,
@@ -159,19 +176,22 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
                      "traffic": None,
-                     "kernel": "k_gemm_stream<5,f32,gen>",
+                     "kernel": "k_gemm_stream<5, f32, generated Omega>",
+                     "bytes_per_launch": "536870912 (row share) / 4294967296 (column layout)",
                      "launches": n_launch,
                      "avg_launch_us": round(1e3 * tot_ms / n_launch, 2)},
         "extra": {"hbm_frac_of_value": round(value / HBM_PEAK_GBPS, 4),
                   "row_layout_GBps": round(rate["row"], 1),
                   "col_layout_GBps": round(rate["col"], 1),
-                  "row_launch_us": round(avg_us["row"], 2),
-                  "col_launch_us": round(avg_us["col"], 2),
+                  "row_kernel_us": round(avg_us["row"], 2),
+                  "col_kernel_us": round(avg_us["col"], 2),
+                  "row_reduce_us": round(red_us["row"], 2),
+                  "col_reduce_us": round(red_us["col"], 2),
                   "row_equals_col_bitwise": same,
                   "tflops": round(2 * N * N * k * 2 * args.steps / (total_ms * 1e-3) / 1e12, 3)},
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(A, k, seed, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(A, P, k, seed, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

@@ -83,21 +83,17 @@ int sketch_abi_version(void);
 /* Static text for a status code. */
 const char* sketch_status_string(int status);
 
-/* Bytes of device workspace a call needs (0 if none).
+/* Bytes of device workspace a call needs (0 if none).  The workspace holds
+ * the FP32 partial sums of the column strips between the streaming kernel and
+ * the FP64 reduction kernel of one call; its contents need no preparation.
+ * One workspace serves one call at a time: calls that may run concurrently
+ * (different streams) need separate workspaces.
  *   op = 0: sketch_gen_matmul / sketch_matmul_omega with an n-column A;
  *   op = 1: sketch_gen_matmul_reduce over P blocks whose widths sum to n.
  * The size depends only on (op, a_dtype, m, n, k, P); for op = 1 it is an
  * upper bound valid for any split of n into P blocks.  Returns 0 for
  * invalid arguments. */
 size_t sketch_workspace_size(int op, int a_dtype, int64_t m, int64_t n, int64_t k, int64_t P);
-
-/* Prepare a workspace for first use: zero its `bytes` bytes on `stream`.
- * A workspace must be prepared once after allocation (or be allocated zeroed);
- * its first 256 KiB hold completion counters that every call that completes
- * leaves at zero again, so a prepared workspace serves any later call whose
- * size fits.  One workspace serves one call at a time: calls that overlap in
- * time need separate workspaces. */
-int sketch_workspace_init(void* workspace, size_t bytes, void* stream);
 
 /*
  * The local product of one process's share (Alg. 1, local multiplication with
@@ -116,7 +112,7 @@ int sketch_workspace_init(void* workspace, size_t bytes, void* stream);
  *   Y          device, m x k, storage y_dtype, leading dim ldy >= k.
  *   beta       0: Y = A*Omega;  1: Y = Y + A*Omega (old Y added in FP64).
  *   workspace  device, >= sketch_workspace_size(0, a_dtype, m, n, k, 1) bytes,
- *              prepared (see sketch_workspace_init); may be NULL if that size is 0.
+ *              16-B aligned; may be NULL if that size is 0.
  * m == 0 or k == 0: nothing to do.  n == 0: Y = 0 (beta 0) or unchanged.
  */
 int sketch_gen_matmul(const void* A, int a_dtype, int64_t m, int64_t n, int64_t lda,
@@ -147,6 +143,18 @@ int sketch_gen_matmul_reduce(const void* const* A_b, int64_t P, int a_dtype, int
                              const float* const* a_scales_b, uint64_t seed, int64_t omega_col0,
                              int64_t k, void* Y, int y_dtype, int64_t ldy, int beta,
                              void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * Per-phase timing (instrumentation; the paper times each phase separately,
+ * Sec. 6): arms the NEXT product call made by this host thread
+ * (sketch_gen_matmul, sketch_gen_matmul_reduce or sketch_matmul_omega) to
+ * record the given HIP events (hipEvent_t, created by the caller) on its
+ * stream: ev_begin before the streaming kernel, ev_mid after it, ev_end after
+ * the FP64 reduction (ev_mid and ev_end are recorded together when no
+ * reduction is needed).  Each pointer may be NULL.  The arming is consumed by
+ * that call (also when it fails validation); pass three NULLs to disarm.
+ */
+int sketch_trace_events(void* ev_begin, void* ev_mid, void* ev_end);
 
 /*
  * Materialise Omega(seed)[row0 : row0+n, col0 : col0+k] into device memory

@@ -59,7 +59,6 @@ def lib() -> ctypes.CDLL:
         L.sketch_status_string.restype = ctypes.c_char_p
         L.sketch_workspace_size.argtypes = [i32, i32, i64, i64, i64, i64]
         L.sketch_workspace_size.restype = sz
-        L.sketch_workspace_init.argtypes = [P, sz, P]
         L.sketch_gen_matmul.argtypes = [P, i32, i64, i64, i64, P, u64, i64, i64, i64, P, i32, i64,
                                         i32, P, sz, P]
         L.sketch_gen_matmul_reduce.argtypes = [P, i64, i32, i64, P, P, P, P, u64, i64, i64, P, i32,
@@ -69,9 +68,10 @@ def lib() -> ctypes.CDLL:
                                           P, sz, P]
         L.sketch_philox_raw.argtypes = [P, u64, P, i64, P]
         L.sketch_quantize.argtypes = [P, i64, i64, i64, i32, P, i64, P, P]
-        for f in ("sketch_workspace_init", "sketch_gen_matmul", "sketch_gen_matmul_reduce",
+        L.sketch_trace_events.argtypes = [P, P, P]
+        for f in ("sketch_gen_matmul", "sketch_gen_matmul_reduce",
                   "sketch_gen_omega", "sketch_matmul_omega", "sketch_philox_raw",
-                  "sketch_quantize"):
+                  "sketch_quantize", "sketch_trace_events"):
             getattr(L, f).restype = i32
         _lib = L
         return L
@@ -133,17 +133,16 @@ _ws_cache: dict = {}
 
 
 def workspace_for(nbytes: int, device, stream_ptr: int) -> tuple[int, int]:
-    """A prepared (zeroed) workspace of at least nbytes for (device, stream).
+    """A cached workspace of at least nbytes for (device, stream).
 
-    The library leaves a workspace prepared after every completed call, so the
-    cached buffer is reused as is; calls on one stream never overlap in time.
+    Calls on one stream run one after the other, so they can share it.
     """
     if nbytes == 0:
         return 0, 0
     key = (torch.device(device).index, stream_ptr)
     buf = _ws_cache.get(key)
     if buf is None or buf.numel() < nbytes:
-        buf = torch.zeros(max(nbytes, 1 << 20), dtype=torch.uint8, device=device)
+        buf = torch.empty(max(nbytes, 1 << 20), dtype=torch.uint8, device=device)
         _ws_cache[key] = buf
     return int(buf.data_ptr()), int(buf.numel())
 
@@ -153,11 +152,6 @@ def workspace_for(nbytes: int, device, stream_ptr: int) -> tuple[int, int]:
 # ----------------------------------------------------------------------------
 def sketch_workspace_size(op: int, a_dtype: int, m: int, n: int, k: int, P: int = 1) -> int:
     return int(lib().sketch_workspace_size(op, a_dtype, m, n, k, P))
-
-
-def sketch_workspace_init(ws: torch.Tensor, stream=None) -> None:
-    _check(lib().sketch_workspace_init(_ptr(ws), ws.numel() * ws.element_size(),
-                                       _stream(stream, ws.device)), "sketch_workspace_init")
 
 
 def _out(Y, m, k, y_dtype, device):
@@ -270,6 +264,11 @@ def sketch_philox_raw(ctr: torch.Tensor, seed: int, *, out: torch.Tensor | None 
     return out
 
 
+def sketch_trace_events(ev_begin, ev_mid, ev_end) -> None:
+    """Arm per-phase HIP events (raw hipEvent_t handles) for this thread's next product call."""
+    _check(lib().sketch_trace_events(ev_begin, ev_mid, ev_end), "sketch_trace_events")
+
+
 def sketch_quantize(A: torch.Tensor, dst: str, *, stream=None):
     """Low-precision copy of A: ('bf16' -> (Aq bfloat16, None)); ('fp8' -> (Aq uint8 codes, scales))."""
     m, n = A.shape
@@ -294,6 +293,6 @@ def sketch_quantize(A: torch.Tensor, dst: str, *, stream=None):
 
 
 __all__ = ["sketch_abi_version", "sketch_status_string", "sketch_workspace_size",
-           "sketch_workspace_init", "sketch_gen_matmul", "sketch_gen_matmul_reduce",
+           "sketch_gen_matmul", "sketch_gen_matmul_reduce",
            "sketch_gen_omega", "sketch_matmul_omega", "sketch_philox_raw", "sketch_quantize",
-           "SketchError", "lib", "LIB_PATH"]
+           "sketch_trace_events", "SketchError", "lib", "LIB_PATH"]

@@ -22,6 +22,15 @@ bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
 int from_hip(hipError_t e) { return e == hipSuccess ? SK_OK : SK_EHIP; }
 
+// Events armed by sketch_trace_events for the next product call of this thread.
+thread_local sk::TraceEvents g_trace;
+
+sk::TraceEvents take_trace() {
+    sk::TraceEvents t = g_trace;
+    g_trace = sk::TraceEvents{};
+    return t;
+}
+
 // Checks shared by every product call; fills the Y part of the launch.
 int check_common(int a_dtype, int64_t m, int64_t k, int64_t col0, const void* Y, int y_dtype,
                  int64_t ldy, int beta) {
@@ -62,10 +71,15 @@ int check_workspace(size_t need, const void* ws, size_t bytes) {
 }
 
 int run_product(sk::GemmLaunch& g, int64_t n_total) {
-    if (g.m == 0 || g.k == 0) return SK_OK;
-    if (n_total == 0) {
-        if (g.beta) return SK_OK;
-        return from_hip(sk::launch_zero_matrix(g.Y, g.y_f64, g.m, g.k, g.ldy, g.stream));
+    if (g.m == 0 || g.k == 0 || n_total == 0) {
+        const sk::TraceEvents& t = g.trace;
+        for (hipEvent_t e : {t.begin, t.mid}) if (e) (void)hipEventRecord(e, g.stream);
+        if (g.m > 0 && g.k > 0 && !g.beta) {
+            const int st = from_hip(sk::launch_zero_matrix(g.Y, g.y_f64, g.m, g.k, g.ldy, g.stream));
+            if (st != SK_OK) return st;
+        }
+        if (t.end) (void)hipEventRecord(t.end, g.stream);
+        return SK_OK;
     }
     return from_hip(sk::launch_gemm_stream(g));
 }
@@ -100,10 +114,11 @@ size_t sketch_workspace_size(int op, int a_dtype, int64_t m, int64_t n, int64_t 
     return workspace_for(op, m, n, k, P);
 }
 
-int sketch_workspace_init(void* workspace, size_t bytes, void* stream) {
-    if (bytes == 0) return SK_OK;
-    if (workspace == nullptr) return SK_EINVAL;
-    return from_hip(sk::launch_zero(workspace, bytes, static_cast<hipStream_t>(stream)));
+int sketch_trace_events(void* ev_begin, void* ev_mid, void* ev_end) {
+    g_trace.begin = static_cast<hipEvent_t>(ev_begin);
+    g_trace.mid = static_cast<hipEvent_t>(ev_mid);
+    g_trace.end = static_cast<hipEvent_t>(ev_end);
+    return SK_OK;
 }
 
 static int gen_matmul_impl(const void* A, int a_dtype, int64_t m, int64_t n, int64_t lda,
@@ -111,6 +126,7 @@ static int gen_matmul_impl(const void* A, int a_dtype, int64_t m, int64_t n, int
                            int64_t omega_col0, const float* Omega, int64_t ldo, int64_t k,
                            void* Y, int y_dtype, int64_t ldy, int beta, void* workspace,
                            size_t workspace_bytes, void* stream) {
+    const sk::TraceEvents trace = take_trace();
     int st = check_common(a_dtype, m, k, omega_col0, Y, y_dtype, ldy, beta);
     if (st != SK_OK) return st;
     st = check_block(A, a_dtype, m, n, lda, omega_row0, a_scales);
@@ -139,6 +155,7 @@ static int gen_matmul_impl(const void* A, int a_dtype, int64_t m, int64_t n, int
     g.workspace = workspace;
     g.workspace_bytes = workspace_bytes;
     g.stream = static_cast<hipStream_t>(stream);
+    g.trace = trace;
     return run_product(g, n);
 }
 
@@ -165,6 +182,7 @@ int sketch_gen_matmul_reduce(const void* const* A_b, int64_t P, int a_dtype, int
                              const float* const* a_scales_b, uint64_t seed, int64_t omega_col0,
                              int64_t k, void* Y, int y_dtype, int64_t ldy, int beta,
                              void* workspace, size_t workspace_bytes, void* stream) {
+    const sk::TraceEvents trace = take_trace();
     int st = check_common(a_dtype, m, k, omega_col0, Y, y_dtype, ldy, beta);
     if (st != SK_OK) return st;
     if (P < 1 || P > sk::kMaxBlocks) return SK_EINVAL;
@@ -196,6 +214,7 @@ int sketch_gen_matmul_reduce(const void* const* A_b, int64_t P, int a_dtype, int
     g.workspace = workspace;
     g.workspace_bytes = workspace_bytes;
     g.stream = static_cast<hipStream_t>(stream);
+    g.trace = trace;
     const int64_t S = sk::count_strips(g, (int)(k < sk::kColGroup ? k : sk::kColGroup));
     st = check_workspace(n_total > 0 ? sk::gemm_workspace_bytes(m, S, k) : 0, workspace,
                          workspace_bytes);

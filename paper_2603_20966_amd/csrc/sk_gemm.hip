@@ -14,11 +14,15 @@
 //     loading 16 contiguous bytes of A per step (a 256-byte coalesced row
 //     segment), multiplying by the matching Omega values from LDS with FP32
 //     FMAs into per-lane accumulators;
+//   * the first loads of A are issued before the Omega slice is generated,
+//     and each wave keeps two steps of loads in flight across its passes;
 //   * the 16 lanes of a row are summed by a fixed DPP butterfly, giving the
 //     FP32 partial of (row, strip, column); partials go to the workspace;
-//   * the last workgroup to finish a row block (device-scope counter) sums
-//     the partials of all strips of that row block in FP64, in strip order,
-//     adds beta * Y, rounds once and writes Y.
+//   * a second small kernel sums the partials of all strips in FP64, in strip
+//     order, adds beta * Y, rounds once and writes Y.  (No cross-workgroup
+//     synchronisation inside the streaming kernel: device-scope release /
+//     acquire would write back and invalidate the L2 of an XCD under every
+//     streaming wave.)
 // The summation order depends only on the strip boundaries, never on m, R or
 // the grid, so results are bitwise reproducible and layout independent.
 #include "sk_device.hpp"
@@ -40,7 +44,6 @@ struct KArgs {
     const float* omega;
     void* Y;
     float* partials;
-    uint32_t* counters;
     uint32_t key0, key1;
     uint32_t col0;
     int P;
@@ -125,6 +128,13 @@ __device__ __forceinline__ float row16_sum(float v) {
     return v;
 }
 
+// Workgroup barrier ordering LDS only: outstanding global loads stay in flight.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 template <int K, int ADT, bool GEN>
 __global__ __launch_bounds__(kWgThreads) void k_gemm_stream(const KArgs args) {
     constexpr int es = Elem<ADT>::size;
@@ -134,7 +144,6 @@ __global__ __launch_bounds__(kWgThreads) void k_gemm_stream(const KArgs args) {
     constexpr int T = C / STEP;                  // steps per full strip
     static_assert(C % STEP == 0, "strip must hold whole steps");
     __shared__ float om[K][C];
-    __shared__ uint32_t s_last;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -143,7 +152,7 @@ __global__ __launch_bounds__(kWgThreads) void k_gemm_stream(const KArgs args) {
     const int rho = lane >> 4;
 
     // ---- which block / strip / row block / column group -----------------
-    int strip = blockIdx.x;
+    const int strip = blockIdx.x;
     int b = 0;
     int64_t strip_in_block = strip;
     for (; b < args.P; ++b) {
@@ -161,7 +170,43 @@ __global__ __launch_bounds__(kWgThreads) void k_gemm_stream(const KArgs args) {
     const int64_t row_begin = (int64_t)rb * args.rows_per_wg;
     const int64_t row_end = min<int64_t>(row_begin + args.rows_per_wg, args.m);
 
-    // ---- Omega slice for this strip -> LDS --------------------------------
+    // ---- this wave's rows: passes of 16 rows, 64 rows apart -----------------
+    const unsigned char* Abase = static_cast<const unsigned char*>(blk.A);
+    const int64_t lda_bytes = blk.lda * es;
+    const bool full = (w == C);
+    const int Tr = full ? T : (w + STEP - 1) / STEP;    // steps per pass
+    const int64_t first_pb = row_begin + wave * 16;
+    const int npass = first_pb < row_end ? (int)((row_end - first_pb + kRowQuantum - 1) / kRowQuantum) : 0;
+    const unsigned char* lane_col = Abase + (col_begin + sig * EPL) * es;
+
+    // Steps run pass by pass (16 rows), column step by column step; loads are
+    // issued two steps ahead of the FMAs that consume them.
+    int ip = 0, it_ = 0;   // next step to load: pass, column step
+    int cp = 0, ct = 0;    // next step to consume
+    auto issue = [&](uint4* buf) {
+        if (ip >= npass) return;
+        const int p = ip;
+        const int t = it_;
+        if (++it_ == Tr) {
+            it_ = 0;
+            ++ip;
+        }
+        const int64_t pb = first_pb + (int64_t)p * kRowQuantum;
+        const int cl = t * STEP + sig * EPL;
+#pragma unroll
+        for (int i = 0; i < kRowGroups; ++i) {
+            const int64_t r = min<int64_t>(pb + 4 * i + rho, args.m - 1);
+            const unsigned char* ptr = lane_col + r * lda_bytes + (int64_t)t * STEP * es;
+            if (full || w - cl >= EPL) buf[i] = *reinterpret_cast<const uint4*>(ptr);
+            else buf[i] = load_tail<ADT>(ptr, w - cl);
+        }
+    };
+
+    uint4 b0[kRowGroups], b1[kRowGroups];
+    issue(b0);
+    issue(b1);
+
+    // ---- Omega slice for this strip -> LDS (overlaps the first loads) --------
     if constexpr (GEN) {
         const int64_t g0 = blk.row0 + col_begin;           // global Omega row of column 0
         const int64_t q_lo = g0 >> 2;
@@ -199,91 +244,55 @@ __global__ __launch_bounds__(kWgThreads) void k_gemm_stream(const KArgs args) {
         const int jl = it - c * C;
         if (c >= kg || jl >= w) om[c][jl] = 0.0f;
     }
-    __syncthreads();
+    lds_barrier();
 
-    // ---- stream the rows ---------------------------------------------------
-    const unsigned char* Abase = static_cast<const unsigned char*>(blk.A);
-    const int64_t lda_bytes = blk.lda * es;
-    const bool full = (w == C);
+    // ---- stream: FMA each step, 16-lane sums at the end of each pass ---------
     const bool single = (args.S_total == 1);
     const float* scales = blk.scales;
+    float acc[kRowGroups][K];
+#pragma unroll
+    for (int i = 0; i < kRowGroups; ++i)
+#pragma unroll
+        for (int c = 0; c < K; ++c) acc[i][c] = 0.0f;
 
-    for (int64_t pb = row_begin + wave * 16; pb < row_end; pb += kRowQuantum) {
-        float acc[kRowGroups][K];
-#pragma unroll
-        for (int i = 0; i < kRowGroups; ++i)
-#pragma unroll
-            for (int c = 0; c < K; ++c) acc[i][c] = 0.0f;
-
-        const unsigned char* rp[kRowGroups];
-#pragma unroll
-        for (int i = 0; i < kRowGroups; ++i) {
-            const int64_t r = min<int64_t>(pb + 4 * i + rho, args.m - 1);
-            rp[i] = Abase + r * lda_bytes + (col_begin + sig * EPL) * es;
+    auto consume = [&](const uint4* raw) {
+        const int p = cp;
+        const int t = ct;
+        if (++ct == Tr) {
+            ct = 0;
+            ++cp;
         }
-
-        auto step = [&](const uint4* raw, int t) {
-            float a[kRowGroups][EPL];
+        float a[kRowGroups][EPL];
 #pragma unroll
-            for (int i = 0; i < kRowGroups; ++i) unpack16<ADT>(raw[i], a[i]);
-            const int cl = t * STEP + sig * EPL;
+        for (int i = 0; i < kRowGroups; ++i) unpack16<ADT>(raw[i], a[i]);
+        const int cl = t * STEP + sig * EPL;
 #pragma unroll
-            for (int c = 0; c < K; ++c) {
-                float wv[EPL];
+        for (int c = 0; c < K; ++c) {
+            float wv[EPL];
 #pragma unroll
-                for (int v = 0; v < EPL / 4; ++v) {
-                    const float4 q = *reinterpret_cast<const float4*>(&om[c][cl + 4 * v]);
-                    wv[4 * v + 0] = q.x;
-                    wv[4 * v + 1] = q.y;
-                    wv[4 * v + 2] = q.z;
-                    wv[4 * v + 3] = q.w;
-                }
-#pragma unroll
-                for (int i = 0; i < kRowGroups; ++i)
-#pragma unroll
-                    for (int e = 0; e < EPL; ++e) acc[i][c] = __builtin_fmaf(a[i][e], wv[e], acc[i][c]);
+            for (int v = 0; v < EPL / 4; ++v) {
+                const float4 q = *reinterpret_cast<const float4*>(&om[c][cl + 4 * v]);
+                wv[4 * v + 0] = q.x;
+                wv[4 * v + 1] = q.y;
+                wv[4 * v + 2] = q.z;
+                wv[4 * v + 3] = q.w;
             }
-        };
-
-        if (full) {
-            uint4 cur[kRowGroups], nxt[kRowGroups];
 #pragma unroll
-            for (int i = 0; i < kRowGroups; ++i) cur[i] = *reinterpret_cast<const uint4*>(rp[i]);
+            for (int i = 0; i < kRowGroups; ++i)
 #pragma unroll
-            for (int t = 0; t < T; ++t) {
-                if (t + 1 < T) {
-#pragma unroll
-                    for (int i = 0; i < kRowGroups; ++i)
-                        nxt[i] = *reinterpret_cast<const uint4*>(rp[i] + (int64_t)(t + 1) * STEP * es);
-                }
-                step(cur, t);
-#pragma unroll
-                for (int i = 0; i < kRowGroups; ++i) cur[i] = nxt[i];
-            }
-        } else {
-            const int Tw = (w + STEP - 1) / STEP;
-            for (int t = 0; t < Tw; ++t) {
-                const int cl = t * STEP + sig * EPL;
-                const int nvalid = w - cl;
-                uint4 raw[kRowGroups];
-#pragma unroll
-                for (int i = 0; i < kRowGroups; ++i) {
-                    const unsigned char* p = rp[i] + (int64_t)t * STEP * es;
-                    if (nvalid >= EPL) raw[i] = *reinterpret_cast<const uint4*>(p);
-                    else raw[i] = load_tail<ADT>(p, nvalid);
-                }
-                step(raw, t);
-            }
+                for (int e = 0; e < EPL; ++e) acc[i][c] = __builtin_fmaf(a[i][e], wv[e], acc[i][c]);
         }
-
-        // ---- 16-lane sums and partial write ----------------------------------
+        if (t != Tr - 1) return;
+        // end of pass: row sums and partial (or final) write, then restart
+        const int64_t pb = first_pb + (int64_t)p * kRowQuantum;
 #pragma unroll
         for (int i = 0; i < kRowGroups; ++i) {
             float mine = 0.0f;
 #pragma unroll
             for (int c = 0; c < K; ++c) {
-                const float s = row16_sum(acc[i][c]);
-                if (sig == c) mine = s;
+                const float sum = row16_sum(acc[i][c]);
+                if (sig == c) mine = sum;
+                acc[i][c] = 0.0f;
             }
             const int64_t r = pb + 4 * i + rho;
             if (r < row_end && sig < kg) {
@@ -304,61 +313,66 @@ __global__ __launch_bounds__(kWgThreads) void k_gemm_stream(const KArgs args) {
                 }
             }
         }
-    }
-    if (single) return;
+    };
 
-    // ---- last workgroup of the row block sums the strips in FP64 ------------
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) {
-        uint32_t* ctr = args.counters + (int64_t)cg * args.num_rb + rb;
-        const uint32_t old = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_ACQ_REL,
-                                                    __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t last = (old == (uint32_t)(args.S_total - 1)) ? 1u : 0u;
-        if (last) __hip_atomic_store(ctr, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        s_last = last;
-    }
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    const int64_t nrow = row_end - row_begin;
-    for (int64_t o = tid; o < nrow * kg; o += kWgThreads) {
-        const int64_t r = row_begin + o / kg;
-        const int c = c_base + (int)(o % kg);
-        double y = 0.0;
-        const float* p = args.partials + r * args.k + c;
-        const int64_t sstride = args.m * args.k;
-        for (int s = 0; s < args.S_total; ++s) y += (double)p[(int64_t)s * sstride];
-        if (args.y_f64) {
-            double* Yp = static_cast<double*>(args.Y) + r * args.ldy + c;
-            if (args.beta) y = *Yp + y;
-            *Yp = y;
-        } else {
-            float* Yp = static_cast<float*>(args.Y) + r * args.ldy + c;
-            if (args.beta) y = (double)*Yp + y;
-            *Yp = (float)y;
+    while (cp < npass) {
+        consume(b0);
+        issue(b0);
+        if (cp < npass) {
+            consume(b1);
+            issue(b1);
         }
     }
 }
 
+// Y (=|+=) sum over strips of the FP32 partials, in FP64, strip order fixed;
+// one thread per output element.
+__global__ void k_reduce_partials(const float* __restrict__ partials, int S, int64_t m, int64_t k,
+                                  void* Y, int y_f64, int64_t ldy, int beta) {
+    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= m * k) return;
+    const int64_t r = o / k;
+    const int64_t c = o - r * k;
+    const float* p = partials + o;
+    const int64_t sstride = m * k;
+    double y = 0.0;
+    for (int s = 0; s < S; ++s) y += (double)p[(int64_t)s * sstride];
+    if (y_f64) {
+        double* Yp = static_cast<double*>(Y) + r * ldy + c;
+        if (beta) y += *Yp;
+        *Yp = y;
+    } else {
+        float* Yp = static_cast<float*>(Y) + r * ldy + c;
+        if (beta) y += (double)*Yp;
+        *Yp = (float)y;
+    }
+}
+
 template <int K, int ADT, bool GEN>
-hipError_t launch_k(const KArgs& a, dim3 grid, hipStream_t s) {
+hipError_t launch_k(const KArgs& a, dim3 grid, hipStream_t s, const TraceEvents& tr) {
+    if (tr.begin) (void)hipEventRecord(tr.begin, s);
     hipLaunchKernelGGL((k_gemm_stream<K, ADT, GEN>), grid, dim3(kWgThreads), 0, s, a);
+    if (tr.mid) (void)hipEventRecord(tr.mid, s);
+    if (a.S_total > 1)
+        hipLaunchKernelGGL(k_reduce_partials, dim3((unsigned)((a.m * a.k + 255) / 256)),
+                           dim3(256), 0, s, a.partials, a.S_total, a.m, a.k, a.Y, a.y_f64, a.ldy,
+                           a.beta);
+    if (tr.end) (void)hipEventRecord(tr.end, s);
     return hipGetLastError();
 }
 
 template <int ADT, bool GEN>
-hipError_t dispatch_k(int kc, const KArgs& a, dim3 grid, hipStream_t s) {
+hipError_t dispatch_k(int kc, const KArgs& a, dim3 grid, hipStream_t s, const TraceEvents& tr) {
     switch (kc) {
-    case 1: return launch_k<1, ADT, GEN>(a, grid, s);
-    case 2: return launch_k<2, ADT, GEN>(a, grid, s);
-    case 3: return launch_k<3, ADT, GEN>(a, grid, s);
-    case 4: return launch_k<4, ADT, GEN>(a, grid, s);
-    case 5: return launch_k<5, ADT, GEN>(a, grid, s);
-    case 6: return launch_k<6, ADT, GEN>(a, grid, s);
-    case 8: return launch_k<8, ADT, GEN>(a, grid, s);
-    case 12: return launch_k<12, ADT, GEN>(a, grid, s);
-    default: return launch_k<16, ADT, GEN>(a, grid, s);
+    case 1: return launch_k<1, ADT, GEN>(a, grid, s, tr);
+    case 2: return launch_k<2, ADT, GEN>(a, grid, s, tr);
+    case 3: return launch_k<3, ADT, GEN>(a, grid, s, tr);
+    case 4: return launch_k<4, ADT, GEN>(a, grid, s, tr);
+    case 5: return launch_k<5, ADT, GEN>(a, grid, s, tr);
+    case 6: return launch_k<6, ADT, GEN>(a, grid, s, tr);
+    case 8: return launch_k<8, ADT, GEN>(a, grid, s, tr);
+    case 12: return launch_k<12, ADT, GEN>(a, grid, s, tr);
+    default: return launch_k<16, ADT, GEN>(a, grid, s, tr);
     }
 }
 
@@ -382,7 +396,7 @@ int64_t count_strips(const GemmLaunch& g, int kg) {
 
 size_t gemm_workspace_bytes(int64_t m, int64_t strips, int64_t k) {
     if (strips <= 1) return 0;
-    return kCounterBytes + (size_t)strips * (size_t)m * (size_t)k * sizeof(float);
+    return (size_t)strips * (size_t)m * (size_t)k * sizeof(float);
 }
 
 hipError_t launch_gemm_stream(const GemmLaunch& g) {
@@ -408,20 +422,17 @@ hipError_t launch_gemm_stream(const GemmLaunch& g) {
     // rows per workgroup: a multiple of 64 giving about wg_target() workgroups
     int64_t R = (g.m * S * ncg) / wg_target();
     R = std::max<int64_t>(kRowQuantum, std::min<int64_t>(1024, (R / kRowQuantum) * kRowQuantum));
-    while (ncg * ((g.m + R - 1) / R) > kMaxCounters) R *= 2;   // one counter per tile row
     const int64_t nrb = (g.m + R - 1) / R;
     a.rows_per_wg = (int)R;
     a.num_rb = (int)nrb;
-    if (S > 1) {
-        a.counters = static_cast<uint32_t*>(g.workspace);
-        a.partials = reinterpret_cast<float*>(static_cast<char*>(g.workspace) + kCounterBytes);
-    }
+    if (S > 1) a.partials = static_cast<float*>(g.workspace);
     dim3 grid((unsigned)S, (unsigned)nrb, (unsigned)ncg);
     const bool gen = (g.omega == nullptr);
+    const TraceEvents& tr = g.trace;
     switch (g.adtype) {
-    case 0: return gen ? dispatch_k<0, true>(kc, a, grid, g.stream) : dispatch_k<0, false>(kc, a, grid, g.stream);
-    case 1: return gen ? dispatch_k<1, true>(kc, a, grid, g.stream) : dispatch_k<1, false>(kc, a, grid, g.stream);
-    default: return gen ? dispatch_k<2, true>(kc, a, grid, g.stream) : dispatch_k<2, false>(kc, a, grid, g.stream);
+    case 0: return gen ? dispatch_k<0, true>(kc, a, grid, g.stream, tr) : dispatch_k<0, false>(kc, a, grid, g.stream, tr);
+    case 1: return gen ? dispatch_k<1, true>(kc, a, grid, g.stream, tr) : dispatch_k<1, false>(kc, a, grid, g.stream, tr);
+    default: return gen ? dispatch_k<2, true>(kc, a, grid, g.stream, tr) : dispatch_k<2, false>(kc, a, grid, g.stream, tr);
     }
 }
 

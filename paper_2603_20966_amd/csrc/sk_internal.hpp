@@ -13,11 +13,6 @@ constexpr int kColGroup = 16;      // Omega columns handled by one workgroup
 constexpr int kWgThreads = 256;    // threads per workgroup of the streaming kernel
 constexpr int kRowQuantum = 64;    // rows per workgroup pass (4 waves x 16 rows)
 
-// Workspace layout: completion counters at a fixed place (the first
-// kCounterBytes, zero between calls), FP32 strip partials after them.
-constexpr int64_t kMaxCounters = 65536;
-constexpr size_t kCounterBytes = (size_t)kMaxCounters * 4;
-
 // Register-tile class (template K of the streaming kernel) for a group of
 // kg Omega columns.
 constexpr int k_class(int kg) { return kg <= 6 ? kg : kg <= 8 ? 8 : kg <= 12 ? 12 : 16; }
@@ -40,6 +35,10 @@ struct BlockDesc {
     const float* scales;  // per-128-row scales or nullptr
 };
 
+struct TraceEvents {
+    hipEvent_t begin = nullptr, mid = nullptr, end = nullptr;
+};
+
 struct GemmLaunch {
     int adtype;               // 0 f32, 1 bf16, 2 fp8
     int64_t m;
@@ -57,6 +56,7 @@ struct GemmLaunch {
     void* workspace;
     size_t workspace_bytes;
     hipStream_t stream;
+    TraceEvents trace;
 };
 
 // Number of FP32 strip partials for a set of blocks and a column-group size.

@@ -257,8 +257,8 @@ def test_full_size_shares_sampled_rows():
 
 
 def test_workspace_reused_across_shapes():
-    """A prepared workspace stays valid for later calls of any shape that fits."""
-    ws = torch.zeros(64 << 20, dtype=torch.uint8, device=DEV)
+    """One workspace serves later calls of any shape that fits, whatever it holds."""
+    ws = torch.full((64 << 20,), 0x7F, dtype=torch.uint8, device=DEV)
     shapes = [(2048, 2048, 5), (300, 5000, 5), (1000, 9000, 16), (64, 3000, 3), (2048, 2048, 5)]
     for m, n, k in shapes:
         A = normal_matrix(m, n, seed=m + n + k)
@@ -268,5 +268,3 @@ def test_workspace_reused_across_shapes():
                                                             device=DEV))
         assert torch.equal(Y, Yfresh)
         check_fp32(Y, A, 5, 0, 0, k)
-    # counters are back at zero after the calls
-    assert not ws[:256 * 1024].any()
