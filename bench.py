@@ -35,6 +35,8 @@ def parse():
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="also run a plain 1 GiB device copy (known traffic) for counter scaling")
     p.add_argument("--cpu-seconds", type=float, default=10.0,
                    help="minimum duration of the oracle's timed run")
     return p.parse_args()
@@ -190,6 +192,15 @@ def main():
                   "row_equals_col_bitwise": same,
                   "tflops": round(2 * N * N * k * 2 * args.steps / (total_ms * 1e-3) / 1e12, 3)},
     }
+    if args.copy_calibration:
+        # a plain copy kernel reading and writing exactly 1 GiB, 3 times: its
+        # FETCH_SIZE / WRITE_SIZE per dispatch calibrate the streaming kernel's counters
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).normal_()
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = {"read": src.numel() * 4, "write": dst.numel() * 4}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, P, k, seed, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -57,8 +57,8 @@ int check_block(const void* A, int a_dtype, int64_t m, int64_t n, int64_t lda, i
     return SK_OK;
 }
 
-size_t workspace_for(int op, int64_t m, int64_t n, int64_t k, int64_t P) {
-    const int64_t C = sk::strip_width_for_k(k);
+size_t workspace_for(int op, int adtype, int64_t m, int64_t n, int64_t k, int64_t P) {
+    const int64_t C = sk::strip_width_for(adtype, k);
     const int64_t S = (op == 0) ? (n + C - 1) / C : n / C + P;
     return sk::gemm_workspace_bytes(m, S, k);
 }
@@ -81,7 +81,8 @@ int run_product(sk::GemmLaunch& g, int64_t n_total) {
         if (t.end) (void)hipEventRecord(t.end, g.stream);
         return SK_OK;
     }
-    return from_hip(sk::launch_gemm_stream(g));
+    return from_hip(sk::use_mfma(g.adtype, g.k) ? sk::launch_gemm_mfma(g)
+                                                 : sk::launch_gemm_stream(g));
 }
 
 }  // namespace
@@ -111,7 +112,7 @@ size_t sketch_workspace_size(int op, int a_dtype, int64_t m, int64_t n, int64_t 
         return 0;
     if (op == 0) P = 1;
     if (P < 1 || P > sk::kMaxBlocks || m == 0 || k == 0 || n == 0) return 0;
-    return workspace_for(op, m, n, k, P);
+    return workspace_for(op, a_dtype, m, n, k, P);
 }
 
 int sketch_trace_events(void* ev_begin, void* ev_mid, void* ev_end) {
@@ -136,7 +137,8 @@ static int gen_matmul_impl(const void* A, int a_dtype, int64_t m, int64_t n, int
         if (n > 0 && (Omega == nullptr || ldo < k)) return SK_EINVAL;
         if (((uintptr_t)Omega & 3u) != 0) return SK_EALIGN;
     }
-    st = check_workspace(n > 0 ? workspace_for(0, m, n, k, 1) : 0, workspace, workspace_bytes);
+    st = check_workspace(n > 0 ? workspace_for(0, a_dtype, m, n, k, 1) : 0, workspace,
+                         workspace_bytes);
     if (st != SK_OK) return st;
     sk::GemmLaunch g{};
     g.adtype = a_dtype;
@@ -215,7 +217,7 @@ int sketch_gen_matmul_reduce(const void* const* A_b, int64_t P, int a_dtype, int
     g.workspace_bytes = workspace_bytes;
     g.stream = static_cast<hipStream_t>(stream);
     g.trace = trace;
-    const int64_t S = sk::count_strips(g, (int)(k < sk::kColGroup ? k : sk::kColGroup));
+    const int64_t S = sk::count_strips(g);
     st = check_workspace(n_total > 0 ? sk::gemm_workspace_bytes(m, S, k) : 0, workspace,
                          workspace_bytes);
     if (st != SK_OK) return st;

@@ -22,9 +22,15 @@ constexpr int k_class(int kg) { return kg <= 6 ? kg : kg <= 8 ? 8 : kg <= 12 ? 1
 // launch shape.
 constexpr int strip_width(int kclass) { return kclass <= 8 ? 1024 : 512; }
 
-// Strip width used for a sketch of width k (first column group).
-constexpr int64_t strip_width_for_k(int64_t k) {
-    return strip_width(k_class((int)(k < kColGroup ? k : kColGroup)));
+// The matrix-core kernel takes FP32 A with a sketch wider than one column
+// group; its strips are 2048 columns.
+constexpr int kMfmaStrip = 2048;
+constexpr bool use_mfma(int adtype, int64_t k) { return adtype == 0 && k > kColGroup; }
+
+// Strip width used for a sketch of width k with A stored as adtype.
+constexpr int64_t strip_width_for(int adtype, int64_t k) {
+    return use_mfma(adtype, k) ? kMfmaStrip
+                               : strip_width(k_class((int)(k < kColGroup ? k : kColGroup)));
 }
 
 struct BlockDesc {
@@ -59,11 +65,14 @@ struct GemmLaunch {
     TraceEvents trace;
 };
 
-// Number of FP32 strip partials for a set of blocks and a column-group size.
-int64_t count_strips(const GemmLaunch& g, int kg);
+// Number of FP32 strip partials of a launch.
+int64_t count_strips(const GemmLaunch& g);
 size_t gemm_workspace_bytes(int64_t m, int64_t strips, int64_t k);
 
 hipError_t launch_gemm_stream(const GemmLaunch& g);
+hipError_t launch_gemm_mfma(const GemmLaunch& g);
+hipError_t launch_reduce_partials(const float* partials, int S, int64_t m, int64_t k, void* Y,
+                                  int y_f64, int64_t ldy, int beta, hipStream_t s);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_zero_matrix(void* Y, int f64, int64_t m, int64_t k, int64_t ldy, hipStream_t s);
 hipError_t launch_philox_raw(const uint32_t* ctr, uint64_t seed, uint32_t* out, int64_t N,

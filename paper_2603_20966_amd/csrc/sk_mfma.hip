@@ -1,0 +1,293 @@
+// Matrix-core kernel for Y = A * Omega(seed) with a wide sketch (k > 16) on gfx950.
+//
+// Once k is large the product is a dense contraction (2k flops per A element,
+// past the FP32 ridge at k ~ 20), so the local multiplication of Alg. 1 runs on
+// the MFMA units: v_mfma_f32_16x16x4f32, FP32 in, FP32 accumulate.
+//
+// Tile of one workgroup (256 threads = 4 waves): 256 rows of A x a strip of
+// kMfmaStrip contraction columns x BN = 16*NT sketch columns.  Each wave owns
+// 64 rows (4 M-tiles of 16) x NT N-tiles, i.e. 4*NT accumulator tiles.
+//
+// Contraction in chunks of 16 columns:
+//   * A goes straight from HBM into the MFMA A-operand layout: lane (g, i)
+//     (g = lane/16, i = lane%16) loads the 16 bytes A[row i][kc+4g .. kc+4g+3]
+//     of each M-tile; component s feeds MFMA s, whose contraction index g then
+//     stands for column kc+4g+s.  Any order of the contraction is a valid
+//     product, so no shuffle is needed.
+//   * Omega for the chunk (16 x BN) is generated from the seed into one half of
+//     a double-buffered LDS tile, laid out [column][16 + 4 pad] so that lane
+//     (g, j) reads Omega[kc+4g .. kc+4g+3][j] as one conflict-free
+//     ds_read_b128: exactly the B operands of the same four MFMAs.
+//   * The next chunk's Omega is generated while this chunk's MFMAs run (VALU
+//     and matrix cores work in parallel); one LDS-only barrier per chunk.
+// Strip partials are FP32 in [S][m][k]; the FP64 strip sum is the shared
+// reduction kernel.  The order of every sum depends only on the strip
+// boundaries, so results are layout independent and reproducible.
+#include "sk_device.hpp"
+#include "sk_internal.hpp"
+
+#pragma clang fp contract(off)
+
+namespace sk {
+namespace {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+
+constexpr int kTM = 4;        // M-tiles (16 rows) per wave
+constexpr int kBM = 4 * kTM * 16;   // rows per workgroup
+constexpr int kKC = 16;       // contraction columns per chunk
+constexpr int kLdsRow = 20;   // floats per LDS column (16 + 4 pad)
+
+struct MArgs {
+    int64_t m;
+    int64_t k;
+    int64_t ldy;
+    int64_t ldo;
+    const float* omega;
+    void* Y;
+    float* partials;
+    uint32_t key0, key1;
+    uint32_t col0;
+    int P;
+    int S_total;
+    int y_f64;
+    int beta;
+    BlockDesc blk[kMaxBlocks];
+};
+
+__device__ __forceinline__ void lds_barrier_m() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+template <int NT, bool GEN>
+__global__ __launch_bounds__(256) void k_gemm_mfma(const MArgs args) {
+    constexpr int BN = 16 * NT;
+    __shared__ float om[2][BN][kLdsRow];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int g = lane >> 4;      // contraction group of the lane (A and B operands)
+    const int i16 = lane & 15;    // row (A operand) / column (B operand) within a tile
+
+    // ---- strip, row block, column block --------------------------------------
+    const int strip = blockIdx.x;
+    int b = 0;
+    int64_t sib = strip;
+    for (; b < args.P; ++b) {
+        const int64_t sb = (args.blk[b].n + kMfmaStrip - 1) / kMfmaStrip;
+        if (sib < sb) break;
+        sib -= sb;
+    }
+    const BlockDesc blk = args.blk[b];
+    const int64_t col_begin = sib * kMfmaStrip;
+    const int w = (int)min<int64_t>(kMfmaStrip, blk.n - col_begin);
+    const int nchunks = (w + kKC - 1) / kKC;
+    const int64_t row_base = (int64_t)blockIdx.y * kBM + wave * (kTM * 16);
+    const int n_base = blockIdx.z * BN;                 // first sketch column of the block
+    const int kb = (int)min<int64_t>(BN, args.k - n_base);
+
+    // ---- A operand loads ----------------------------------------------------------
+    const unsigned char* Ab = static_cast<const unsigned char*>(blk.A);
+    const int64_t lda4 = blk.lda * 4;
+    const unsigned char* arow[kTM];
+#pragma unroll
+    for (int tm = 0; tm < kTM; ++tm) {
+        const int64_t r = min<int64_t>(row_base + tm * 16 + i16, args.m - 1);
+        arow[tm] = Ab + r * lda4 + (col_begin + 4 * g) * 4;
+    }
+    auto load_a = [&](v4f* a, int c) {
+        if (c >= nchunks) return;
+        const int kl = c * kKC + 4 * g;               // local column of component 0
+#pragma unroll
+        for (int tm = 0; tm < kTM; ++tm) {
+            const unsigned char* p = arow[tm] + (int64_t)c * kKC * 4;
+            if (kl + 3 < w) {
+                a[tm] = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(p));
+            } else {
+                v4f v = {0.f, 0.f, 0.f, 0.f};
+                const float* pf = reinterpret_cast<const float*>(p);
+                for (int e = 0; e < 4; ++e)
+                    if (kl + e < w) v[e] = pf[e];
+                a[tm] = v;
+            }
+        }
+    };
+
+    // ---- Omega chunk -> LDS ----------------------------------------------------------
+    // zero the columns past k once: generation never writes them
+    for (int it = tid; it < 2 * BN * kLdsRow; it += 256) {
+        const int n = (it / kLdsRow) % BN;
+        if (n >= kb) (&om[0][0][0])[it] = 0.0f;
+    }
+    auto make_chunk = [&](int c) {
+        const int buf = c & 1;
+        const int kvalid = min(kKC, w - c * kKC);
+        if constexpr (GEN) {
+            const int64_t g0 = blk.row0 + col_begin + (int64_t)c * kKC;  // global Omega row of local 0
+            const int64_t q_lo = g0 >> 2;
+            const int nq = (int)(((g0 + kKC - 1) >> 2) - q_lo + 1);       // 4, or 5 if unaligned
+            const int items = nq * kb;
+            for (int it = tid; it < items; it += 256) {
+                const int qi = it / kb;
+                const int n = it - qi * kb;
+                const float4 z = omega4((uint64_t)(q_lo + qi), args.col0 + (uint32_t)(n_base + n),
+                                        args.key0, args.key1);
+                const int kl0 = (int)(4 * (q_lo + qi) - g0);
+                if (kl0 >= 0 && (kl0 & 3) == 0 && kl0 + 3 < kvalid) {
+                    *reinterpret_cast<float4*>(&om[buf][n][kl0]) = z;
+                } else {
+                    const float zz[4] = {z.x, z.y, z.z, z.w};
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const int kl = kl0 + t;
+                        if (kl >= 0 && kl < kKC) om[buf][n][kl] = (kl < kvalid) ? zz[t] : 0.0f;
+                    }
+                }
+            }
+        } else {
+            for (int it = tid; it < kKC * kb; it += 256) {
+                const int kl = it / kb;
+                const int n = it - kl * kb;
+                om[buf][n][kl] = (kl < kvalid)
+                                     ? args.omega[(col_begin + (int64_t)c * kKC + kl) * args.ldo + n_base + n]
+                                     : 0.0f;
+            }
+        }
+    };
+
+    v4f acc[kTM][NT];
+#pragma unroll
+    for (int tm = 0; tm < kTM; ++tm)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[tm][nt] = v4f{0.f, 0.f, 0.f, 0.f};
+
+    v4f a0[kTM], a1[kTM];
+    load_a(a0, 0);
+    load_a(a1, 1);
+    make_chunk(0);
+    lds_barrier_m();
+
+    auto compute = [&](const v4f* a, int c) {
+        const int buf = c & 1;
+        v4f bop[NT];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+            bop[nt] = *reinterpret_cast<const v4f*>(&om[buf][nt * 16 + i16][4 * g]);
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int tm = 0; tm < kTM; ++tm)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+                    acc[tm][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[tm][s], bop[nt][s],
+                                                                        acc[tm][nt], 0, 0, 0);
+    };
+
+    for (int c = 0; c < nchunks; c += 2) {
+        if (c + 1 < nchunks) make_chunk(c + 1);
+        compute(a0, c);
+        load_a(a0, c + 2);
+        lds_barrier_m();
+        if (c + 1 < nchunks) {
+            if (c + 2 < nchunks) make_chunk(c + 2);
+            compute(a1, c + 1);
+            load_a(a1, c + 3);
+            lds_barrier_m();
+        }
+    }
+
+    // ---- write: lane (g, j) holds rows 4g..4g+3, column j of each tile ----------------
+    const bool single = (args.S_total == 1);
+    const float* scales = blk.scales;
+#pragma unroll
+    for (int tm = 0; tm < kTM; ++tm) {
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const int cn = nt * 16 + i16;
+            if (cn >= kb) continue;
+            const int64_t col = n_base + cn;
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                const int64_t r = row_base + tm * 16 + 4 * g + rr;
+                if (r >= args.m) continue;
+                float v = acc[tm][nt][rr];
+                if (scales) v *= scales[r >> 7];
+                if (single) {
+                    double y = (double)v;
+                    if (args.y_f64) {
+                        double* Yp = static_cast<double*>(args.Y) + r * args.ldy + col;
+                        if (args.beta) y += *Yp;
+                        *Yp = y;
+                    } else {
+                        float* Yp = static_cast<float*>(args.Y) + r * args.ldy + col;
+                        if (args.beta) y += (double)*Yp;
+                        *Yp = (float)y;
+                    }
+                } else {
+                    args.partials[((int64_t)strip * args.m + r) * args.k + col] = v;
+                }
+            }
+        }
+    }
+}
+
+template <int NT, bool GEN>
+hipError_t launch_m(const MArgs& a, dim3 grid, hipStream_t s) {
+    hipLaunchKernelGGL((k_gemm_mfma<NT, GEN>), grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+template <bool GEN>
+hipError_t dispatch_m(int nt, const MArgs& a, dim3 grid, hipStream_t s) {
+    switch (nt) {
+    case 2: return launch_m<2, GEN>(a, grid, s);
+    case 4: return launch_m<4, GEN>(a, grid, s);
+    default: return launch_m<8, GEN>(a, grid, s);
+    }
+}
+
+}  // namespace
+
+// N-tiles (of 16 sketch columns) per workgroup for a sketch of width k.
+int mfma_ntiles(int64_t k) { return k <= 32 ? 2 : k <= 64 ? 4 : 8; }
+
+hipError_t launch_gemm_mfma(const GemmLaunch& g) {
+    const int nt = mfma_ntiles(g.k);
+    const int64_t BN = 16 * nt;
+    const int64_t nblk = (g.k + BN - 1) / BN;
+    int64_t S = 0;
+    for (int b = 0; b < g.P; ++b) S += (g.blk[b].n + kMfmaStrip - 1) / kMfmaStrip;
+    MArgs a{};
+    a.m = g.m;
+    a.k = g.k;
+    a.ldy = g.ldy;
+    a.ldo = g.ldo;
+    a.omega = g.omega;
+    a.Y = g.Y;
+    a.partials = S > 1 ? static_cast<float*>(g.workspace) : nullptr;
+    a.key0 = (uint32_t)g.seed;
+    a.key1 = (uint32_t)(g.seed >> 32);
+    a.col0 = g.col0;
+    a.P = g.P;
+    a.S_total = (int)S;
+    a.y_f64 = g.y_f64;
+    a.beta = g.beta;
+    for (int b = 0; b < g.P; ++b) a.blk[b] = g.blk[b];
+    const dim3 grid((unsigned)S, (unsigned)((g.m + kBM - 1) / kBM), (unsigned)nblk);
+    const TraceEvents& tr = g.trace;
+    if (tr.begin) (void)hipEventRecord(tr.begin, g.stream);
+    hipError_t e = (g.omega == nullptr) ? dispatch_m<true>(nt, a, grid, g.stream)
+                                        : dispatch_m<false>(nt, a, grid, g.stream);
+    if (e != hipSuccess) return e;
+    if (tr.mid) (void)hipEventRecord(tr.mid, g.stream);
+    if (S > 1) e = launch_reduce_partials(a.partials, (int)S, g.m, g.k, g.Y, g.y_f64, g.ldy,
+                                          g.beta, g.stream);
+    if (tr.end) (void)hipEventRecord(tr.end, g.stream);
+    return e;
+}
+
+}  // namespace sk

@@ -1,0 +1,107 @@
+"""GPU parity of the precision form: A stored in BF16 or FP8-E4M3 (per-128-row
+power-of-two scales), products accumulated in FP32, strips summed in FP64.
+
+* quantised codes and scales: bit-exact against the oracle's codecs;
+* Y against the oracle on the dequantised A: within the FP32 summation bound
+  (the quantisation is exact input data, so this isolates the arithmetic);
+* Y against the oracle on the original FP32 A (end-to-end error): relative
+  Frobenius <= 1e-2 for BF16 (the stated target); for FP8 the error is reported
+  and held to the model's order (3 mantissa bits: <= 5e-2).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2603_20966_amd as sk
+from sketch_inputs import normal_matrix
+
+pytestmark = pytest.mark.gpu
+
+U = 2.0 ** -24
+DEV = "cuda:0"
+
+
+def dev_f32(x):
+    ld = (x.shape[1] + 3) // 4 * 4
+    buf = torch.zeros((x.shape[0], max(ld, 4)), dtype=torch.float32, device=DEV)
+    buf[:, :x.shape[1]] = torch.from_numpy(x).to(DEV)
+    return buf[:, :x.shape[1]]
+
+
+@pytest.mark.parametrize("m,n", [(300, 5000), (128, 1024), (1, 7), (257, 2049)])
+def test_bf16_codes_bit_exact(m, n):
+    A = normal_matrix(m, n, seed=m + n) * np.float32(3.0)
+    Aq, sc = sk.sketch_quantize(dev_f32(A), "bf16")
+    assert sc is None
+    got = Aq.cpu().view(torch.int16).numpy().view(np.uint16)
+    assert np.array_equal(got, oracle.bf16_encode(A))
+
+
+@pytest.mark.parametrize("m,n", [(300, 5000), (128, 1024), (1, 7), (257, 2049)])
+def test_fp8_codes_and_scales_bit_exact(m, n):
+    A = normal_matrix(m, n, seed=2 * m + n) * np.float32(5.0)
+    if m > 128:
+        A[128:256] *= np.float32(1e-4)       # a block with a much smaller scale
+    Aq, sc = sk.sketch_quantize(dev_f32(A), "fp8")
+    Q, s = oracle.quantize_fp8_rows128(A)
+    assert np.array_equal(sc.cpu().numpy(), s)
+    assert np.array_equal(Aq.cpu().numpy(), Q)
+
+
+def test_fp8_zero_block_scale_is_one():
+    A = np.zeros((200, 64), dtype=np.float32)
+    A[:128] = normal_matrix(128, 64, seed=1)
+    Aq, sc = sk.sketch_quantize(dev_f32(A), "fp8")
+    assert sc.cpu().numpy()[1] == 1.0
+    assert not Aq.cpu().numpy()[128:].any()
+
+
+def _deq_bound(Adeq, Y, seed, row0, k, ref):
+    Om = oracle.omega_block(seed, row0, Adeq.shape[1], 0, k)
+    mag = oracle.matmul(np.abs(Adeq).astype(np.float32), np.abs(Om))
+    err = np.abs(Y - ref)
+    assert (err <= 80 * U * mag + U * np.abs(ref)).all(), float((err - 80 * U * mag).max())
+
+
+@pytest.mark.parametrize("m,n,k,row0", [(300, 5000, 5, 0), (200, 3000, 16, 7), (130, 2100, 40, 4)])
+def test_bf16_product(m, n, k, row0):
+    A = normal_matrix(m, n, seed=3 * m + k)
+    Aq, _ = sk.sketch_quantize(dev_f32(A), "bf16")
+    Y = sk.sketch_gen_matmul(Aq, 11, k, omega_row0=row0).double().cpu().numpy()
+    codes = Aq.cpu().view(torch.int16).numpy().view(np.uint16)
+    ref_q = oracle.gen_matmul_q(codes, "bf16", None, 11, row0, 0, k)
+    Adeq = oracle.bf16_decode(codes)
+    _deq_bound(Adeq, Y, 11, row0, k, ref_q)
+    e2e = oracle.rel_fro(Y, oracle.gen_matmul(A, 11, row0, 0, k))
+    assert e2e <= 1e-2, e2e
+    assert e2e >= 1e-4          # BF16 storage does lose precision: the test sees it
+
+
+@pytest.mark.parametrize("m,n,k,row0", [(300, 5000, 5, 0), (260, 3000, 16, 9)])
+def test_fp8_product(m, n, k, row0):
+    A = normal_matrix(m, n, seed=5 * m + k)
+    A[128:256] *= np.float32(0.01)
+    Aq, sc = sk.sketch_quantize(dev_f32(A), "fp8")
+    Y = sk.sketch_gen_matmul(Aq, 12, k, omega_row0=row0, a_scales=sc).double().cpu().numpy()
+    Q = Aq.cpu().numpy()
+    s = sc.cpu().numpy()
+    ref_q = oracle.gen_matmul_q(Q, "fp8", s, 12, row0, 0, k)
+    Adeq = oracle.fp8_decode_table()[Q] * np.repeat(s.astype(np.float64), 128)[:m, None]
+    _deq_bound(Adeq, Y, 12, row0, k, ref_q)
+    e2e = oracle.rel_fro(Y, oracle.gen_matmul(A, 12, row0, 0, k))
+    assert e2e <= 5e-2, e2e
+
+
+def test_low_precision_reduce_layout_matches_row_layout():
+    """1Dred over BF16 / FP8 column blocks equals the row layout bitwise."""
+    m, n, P = 256, 4096, 4
+    A = normal_matrix(m, n, seed=77)
+    w = n // P
+    for kind in ("bf16", "fp8"):
+        Aq, sc = sk.sketch_quantize(dev_f32(A), kind)
+        Yrow = sk.sketch_gen_matmul(Aq, 3, 5, a_scales=sc)
+        blocks = [Aq[:, b * w:(b + 1) * w] for b in range(P)]
+        Yred = sk.sketch_gen_matmul_reduce(blocks, [b * w for b in range(P)], 3, 5,
+                                           scales=None if sc is None else [sc] * P)
+        assert torch.equal(Yrow, Yred), kind
