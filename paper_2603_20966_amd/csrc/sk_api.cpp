@@ -41,8 +41,9 @@ int check_common(int a_dtype, int64_t m, int64_t k, int64_t col0, const void* Y,
     if (m == 0 || k == 0) return SK_OK;
     if (Y == nullptr || ldy < k) return SK_EINVAL;
     if (((uintptr_t)Y & (y_dtype == SK_Y_F64 ? 7u : 3u)) != 0) return SK_EALIGN;
-    // grid: rows per workgroup are at most 1024, row blocks at most 65535
-    if (m > kMaxGridY * 1024) return SK_EUNSUPPORTED;
+    // grid: rows per workgroup are at most 1024 (streaming kernel) or exactly
+    // 256 (matrix-core kernel), row blocks at most 65535
+    if (m > kMaxGridY * (sk::use_mfma(a_dtype, k) ? 256 : 1024)) return SK_EUNSUPPORTED;
     return SK_OK;
 }
 
