@@ -146,49 +146,58 @@ __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// Everything one workgroup needs for one tile (strip x row range x column
+// group) of one A block and its output.
+struct Tile {
+    const unsigned char* A;   // first element of the A block
+    int64_t lda;              // elements
+    int64_t n;                // columns of the block
+    int64_t row0;             // global Omega row of the block's column 0
+    const float* scales;      // per-128-row scales or nullptr
+    int64_t m, k;             // rows of A and Y, sketch width
+    int64_t col_begin;        // first block column of the strip
+    int64_t row_begin, row_end;
+    int c_base, kg;           // sketch columns [c_base, c_base + kg)
+    uint32_t key0, key1, col0;
+    const float* omega;       // stored operand (n x k, ldo) when not generated
+    int64_t ldo;
+    void* Y;
+    int64_t ldy;
+    int y_f64, beta;
+    float* partials;          // [S][m][k] of the output, or nullptr
+    int64_t strip_index;      // row of this strip in the partial array
+    bool single;              // the output has one strip: write Y directly
+};
+
+// One tile: issue the first A loads, build the Omega slice in LDS, stream the
+// rows, write the strip partials (or Y).  All threads of the workgroup call it.
 template <int K, int ADT, bool GEN>
-__global__ __launch_bounds__(kWgThreads) void k_gemm_stream(const KArgs args) {
+__device__ __forceinline__ void tile_body(const Tile& tl, float (*om)[strip_width(K)]) {
     constexpr int es = Elem<ADT>::size;
     constexpr int EPL = 16 / es;                 // elements per lane step
     constexpr int C = strip_width(K);            // columns per strip
     constexpr int STEP = kLanesPerRow * EPL;     // columns per wave step
     constexpr int T = C / STEP;                  // steps per full strip
     static_assert(C % STEP == 0, "strip must hold whole steps");
-    __shared__ float om[K][C];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int sig = lane & (kLanesPerRow - 1);
     const int rho = lane >> 4;
-
-    // ---- which block / strip / row block / column group -----------------
-    const int strip = blockIdx.x;
-    int b = 0;
-    int64_t strip_in_block = strip;
-    for (; b < args.P; ++b) {
-        const int64_t sb = (args.blk[b].n + C - 1) / C;
-        if (strip_in_block < sb) break;
-        strip_in_block -= sb;
-    }
-    const BlockDesc blk = args.blk[b];
-    const int rb = blockIdx.y;
-    const int cg = blockIdx.z;
-    const int c_base = cg * kColGroup;
-    const int kg = (int)min<int64_t>(kColGroup, args.k - c_base);
-    const int64_t col_begin = strip_in_block * C;   // first A column of the strip
-    const int w = (int)min<int64_t>(C, blk.n - col_begin);
-    const int64_t row_begin = (int64_t)rb * args.rows_per_wg;
-    const int64_t row_end = min<int64_t>(row_begin + args.rows_per_wg, args.m);
+    const int kg = tl.kg;
+    const int c_base = tl.c_base;
+    const int64_t col_begin = tl.col_begin;
+    const int w = (int)min<int64_t>(C, tl.n - col_begin);
+    const int64_t row_end = tl.row_end;
 
     // ---- this wave's rows: passes of 16 rows, 64 rows apart -----------------
-    const unsigned char* Abase = static_cast<const unsigned char*>(blk.A);
-    const int64_t lda_bytes = blk.lda * es;
+    const int64_t lda_bytes = tl.lda * es;
     const bool full = (w == C);
     const int Tr = full ? T : (w + STEP - 1) / STEP;    // steps per pass
-    const int64_t first_pb = row_begin + wave * 16;
+    const int64_t first_pb = tl.row_begin + wave * 16;
     const int npass = first_pb < row_end ? (int)((row_end - first_pb + kRowQuantum - 1) / kRowQuantum) : 0;
-    const unsigned char* lane_col = Abase + (col_begin + sig * EPL) * es;
+    const unsigned char* lane_col = tl.A + (col_begin + sig * EPL) * es;
 
     // Steps run pass by pass (16 rows), column step by column step; loads are
     // issued kDepth steps ahead of the FMAs that consume them.
@@ -206,7 +215,7 @@ __global__ __launch_bounds__(kWgThreads) void k_gemm_stream(const KArgs args) {
         const int cl = t * STEP + sig * EPL;
 #pragma unroll
         for (int i = 0; i < kRowGroups; ++i) {
-            const int64_t r = min<int64_t>(pb + 4 * i + rho, args.m - 1);
+            const int64_t r = min<int64_t>(pb + 4 * i + rho, tl.m - 1);
             const unsigned char* ptr = lane_col + r * lda_bytes + (int64_t)t * STEP * es;
             if (full || w - cl >= EPL) buf[i] = load_a16(ptr);
             else buf[i] = load_tail<ADT>(ptr, w - cl);
@@ -219,7 +228,7 @@ __global__ __launch_bounds__(kWgThreads) void k_gemm_stream(const KArgs args) {
 
     // ---- Omega slice for this strip -> LDS (overlaps the first loads) --------
     if constexpr (GEN) {
-        const int64_t g0 = blk.row0 + col_begin;           // global Omega row of column 0
+        const int64_t g0 = tl.row0 + col_begin;            // global Omega row of column 0
         const int64_t q_lo = g0 >> 2;
         const int64_t q_hi = (g0 + w - 1) >> 2;
         const int nq = (int)(q_hi - q_lo + 1);
@@ -228,8 +237,8 @@ __global__ __launch_bounds__(kWgThreads) void k_gemm_stream(const KArgs args) {
         for (int it = tid; it < items; it += kWgThreads) {
             const int qi = it / kg;
             const int c = it - qi * kg;
-            const float4 z = omega4((uint64_t)(q_lo + qi), args.col0 + (uint32_t)(c_base + c),
-                                    args.key0, args.key1);
+            const float4 z = omega4((uint64_t)(q_lo + qi), tl.col0 + (uint32_t)(c_base + c),
+                                    tl.key0, tl.key1);
             const int64_t p0 = 4 * (q_lo + qi) - g0;       // local column of z.x
             if (aligned && p0 + 3 < w) {
                 *reinterpret_cast<float4*>(&om[c][p0]) = z;
@@ -246,7 +255,7 @@ __global__ __launch_bounds__(kWgThreads) void k_gemm_stream(const KArgs args) {
         for (int it = tid; it < w * kg; it += kWgThreads) {
             const int jl = it / kg;
             const int c = it - jl * kg;
-            om[c][jl] = args.omega[(col_begin + jl) * args.ldo + c_base + c];
+            om[c][jl] = tl.omega[(col_begin + jl) * tl.ldo + c_base + c];
         }
     }
     // zero the unused part of the slice (ragged strip, unused columns)
@@ -258,8 +267,6 @@ __global__ __launch_bounds__(kWgThreads) void k_gemm_stream(const KArgs args) {
     lds_barrier();
 
     // ---- stream: FMA each step, 16-lane sums at the end of each pass ---------
-    const bool single = (args.S_total == 1);
-    const float* scales = blk.scales;
     float acc[kRowGroups][K];
 #pragma unroll
     for (int i = 0; i < kRowGroups; ++i)
@@ -307,20 +314,20 @@ __global__ __launch_bounds__(kWgThreads) void k_gemm_stream(const KArgs args) {
             }
             const int64_t r = pb + 4 * i + rho;
             if (r < row_end && sig < kg) {
-                if (scales) mine *= scales[r >> 7];
-                if (single) {
+                if (tl.scales) mine *= tl.scales[r >> 7];
+                if (tl.single) {
                     double y = (double)mine;
-                    if (args.y_f64) {
-                        double* Yp = static_cast<double*>(args.Y) + r * args.ldy + c_base + sig;
-                        if (args.beta) y += *Yp;
+                    if (tl.y_f64) {
+                        double* Yp = static_cast<double*>(tl.Y) + r * tl.ldy + c_base + sig;
+                        if (tl.beta) y += *Yp;
                         *Yp = y;
                     } else {
-                        float* Yp = static_cast<float*>(args.Y) + r * args.ldy + c_base + sig;
-                        if (args.beta) y += (double)*Yp;
+                        float* Yp = static_cast<float*>(tl.Y) + r * tl.ldy + c_base + sig;
+                        if (tl.beta) y += (double)*Yp;
                         *Yp = (float)y;
                     }
                 } else {
-                    args.partials[((int64_t)strip * args.m + r) * args.k + c_base + sig] = mine;
+                    tl.partials[(tl.strip_index * tl.m + r) * tl.k + c_base + sig] = mine;
                 }
             }
         }
@@ -334,6 +341,96 @@ __global__ __launch_bounds__(kWgThreads) void k_gemm_stream(const KArgs args) {
                 issue(bufs[d]);
             }
         }
+    }
+}
+
+// One call: grid (strips of all blocks, row blocks, column groups), one tile
+// per workgroup; the blocks share the output (contraction split).
+template <int K, int ADT, bool GEN>
+__global__ __launch_bounds__(kWgThreads) void k_gemm_stream(const KArgs args) {
+    constexpr int C = strip_width(K);
+    __shared__ float om[K][C];
+    const int strip = blockIdx.x;
+    int b = 0;
+    int64_t strip_in_block = strip;
+    for (; b < args.P; ++b) {
+        const int64_t sb = (args.blk[b].n + C - 1) / C;
+        if (strip_in_block < sb) break;
+        strip_in_block -= sb;
+    }
+    const BlockDesc& blk = args.blk[b];
+    Tile tl;
+    tl.A = static_cast<const unsigned char*>(blk.A);
+    tl.lda = blk.lda;
+    tl.n = blk.n;
+    tl.row0 = blk.row0;
+    tl.scales = blk.scales;
+    tl.m = args.m;
+    tl.k = args.k;
+    tl.col_begin = strip_in_block * C;
+    tl.row_begin = (int64_t)blockIdx.y * args.rows_per_wg;
+    tl.row_end = min<int64_t>(tl.row_begin + args.rows_per_wg, args.m);
+    tl.c_base = blockIdx.z * kColGroup;
+    tl.kg = (int)min<int64_t>(kColGroup, args.k - tl.c_base);
+    tl.key0 = args.key0;
+    tl.key1 = args.key1;
+    tl.col0 = args.col0;
+    tl.omega = args.omega;
+    tl.ldo = args.ldo;
+    tl.Y = args.Y;
+    tl.ldy = args.ldy;
+    tl.y_f64 = args.y_f64;
+    tl.beta = args.beta;
+    tl.partials = args.partials;
+    tl.strip_index = strip;
+    tl.single = (args.S_total == 1);
+    tile_body<K, ADT, GEN>(tl, om);
+}
+
+// A batch of independent requests (serving): the same tiles as one call per
+// request, walked by a fixed grid; each request keeps its own seed, offsets,
+// output and partial array, so its result does not depend on the batch.
+template <int K, int ADT>
+__global__ __launch_bounds__(kWgThreads) void k_gemm_batch(const BatchArgs args) {
+    constexpr int C = strip_width(K);
+    __shared__ float om[K][C];
+    bool first = true;
+    for (int64_t t = blockIdx.x; t < args.total_tiles; t += gridDim.x) {
+        int q = 0;
+        while (q + 1 < args.count && t >= args.req[q + 1].tile_begin) ++q;
+        const BatchReq& rq = args.req[q];
+        const int64_t lt = t - rq.tile_begin;
+        const int64_t strip = lt % rq.strips;
+        const int64_t rb = (lt / rq.strips) % rq.rowblocks;
+        const int cg = (int)(lt / ((int64_t)rq.strips * rq.rowblocks));
+        Tile tl;
+        tl.A = static_cast<const unsigned char*>(rq.A);
+        tl.lda = rq.lda;
+        tl.n = rq.n;
+        tl.row0 = rq.row0;
+        tl.scales = rq.scales;
+        tl.m = rq.m;
+        tl.k = rq.k;
+        tl.col_begin = strip * C;
+        tl.row_begin = rb * rq.rows_per_wg;
+        tl.row_end = min<int64_t>(tl.row_begin + rq.rows_per_wg, rq.m);
+        tl.c_base = cg * kColGroup;
+        tl.kg = (int)min<int64_t>(kColGroup, rq.k - tl.c_base);
+        tl.key0 = (uint32_t)rq.seed;
+        tl.key1 = (uint32_t)(rq.seed >> 32);
+        tl.col0 = rq.col0;
+        tl.omega = nullptr;
+        tl.ldo = 0;
+        tl.Y = rq.Y;
+        tl.ldy = rq.ldy;
+        tl.y_f64 = rq.y_f64;
+        tl.beta = rq.beta;
+        tl.partials = rq.partials;
+        tl.strip_index = strip;
+        tl.single = (rq.strips == 1);
+        if (!first) lds_barrier();   // every wave is done with the previous slice
+        first = false;
+        tile_body<K, ADT, true>(tl, om);
     }
 }
 
@@ -364,6 +461,41 @@ __global__ void k_reduce_partials(const float* __restrict__ partials, int S, int
     } else {
         float* Yp = static_cast<float*>(Y) + r * ldy + c;
         if (beta) y += (double)*Yp;
+        *Yp = (float)y;
+    }
+}
+
+// Batched FP64 strip sums: one thread per output element of every request
+// with more than one strip, in strip order.
+__global__ void k_reduce_batch(const BatchArgs args) {
+    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= args.total_outputs) return;
+    int q = 0;
+    while (q + 1 < args.count && o >= args.req[q + 1].out_begin) ++q;
+    const BatchReq& rq = args.req[q];
+    if (rq.strips == 1) return;
+    const int64_t lo = o - rq.out_begin;
+    const int64_t r = lo / rq.k;
+    const int64_t c = lo - r * rq.k;
+    const float* p = rq.partials + lo;
+    const int64_t sstride = rq.m * rq.k;
+    double y = 0.0;
+    int s = 0;
+    for (; s + 16 <= rq.strips; s += 16) {
+        float v[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) v[j] = __builtin_nontemporal_load(p + (int64_t)(s + j) * sstride);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) y += (double)v[j];
+    }
+    for (; s < rq.strips; ++s) y += (double)p[(int64_t)s * sstride];
+    if (rq.y_f64) {
+        double* Yp = static_cast<double*>(rq.Y) + r * rq.ldy + c;
+        if (rq.beta) y += *Yp;
+        *Yp = y;
+    } else {
+        float* Yp = static_cast<float*>(rq.Y) + r * rq.ldy + c;
+        if (rq.beta) y += (double)*Yp;
         *Yp = (float)y;
     }
 }
@@ -460,6 +592,30 @@ hipError_t launch_gemm_stream(const GemmLaunch& g) {
     case 1: return gen ? dispatch_k<1, true>(kc, a, grid, g.stream, tr) : dispatch_k<1, false>(kc, a, grid, g.stream, tr);
     default: return gen ? dispatch_k<2, true>(kc, a, grid, g.stream, tr) : dispatch_k<2, false>(kc, a, grid, g.stream, tr);
     }
+}
+
+hipError_t launch_gemm_batch(const BatchArgs& a, int kclass, int adtype, int grid,
+                             hipStream_t s) {
+    if (a.count == 0 || a.total_tiles == 0) return hipSuccess;
+    const dim3 g((unsigned)grid), blk(kWgThreads);
+#define SK_BATCH(KK)                                                                       \
+    case KK:                                                                               \
+        if (adtype == 0) hipLaunchKernelGGL((k_gemm_batch<KK, 0>), g, blk, 0, s, a);       \
+        else if (adtype == 1) hipLaunchKernelGGL((k_gemm_batch<KK, 1>), g, blk, 0, s, a);  \
+        else hipLaunchKernelGGL((k_gemm_batch<KK, 2>), g, blk, 0, s, a);                   \
+        break;
+    switch (kclass) {
+        SK_BATCH(1) SK_BATCH(2) SK_BATCH(3) SK_BATCH(4) SK_BATCH(5) SK_BATCH(6) SK_BATCH(8)
+        SK_BATCH(12) SK_BATCH(16)
+    default: return hipErrorInvalidValue;
+    }
+#undef SK_BATCH
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (a.total_outputs > 0)
+        hipLaunchKernelGGL(k_reduce_batch, dim3((unsigned)((a.total_outputs + 255) / 256)),
+                           dim3(256), 0, s, a);
+    return hipGetLastError();
 }
 
 }  // namespace sk

@@ -65,11 +65,38 @@ struct GemmLaunch {
     TraceEvents trace;
 };
 
+// One request of a serving batch: one A block with its own output.  Tiles of
+// request q are [tile_begin, tile_begin + strips*rowblocks*colgroups); its
+// outputs (for the batched strip sum) are [out_begin, out_begin + m*k).
+constexpr int kMaxBatch = 16;
+struct BatchReq {
+    const void* A;
+    int64_t n, lda, row0;
+    const float* scales;
+    int64_t m, k;
+    void* Y;
+    int64_t ldy;
+    float* partials;        // [strips][m][k] (unused when strips == 1)
+    uint64_t seed;
+    uint32_t col0;
+    int32_t y_f64, beta;
+    int32_t rows_per_wg, strips, rowblocks;
+    int64_t tile_begin, out_begin;
+};
+struct BatchArgs {
+    int count;
+    int64_t total_tiles;
+    int64_t total_outputs;   // outputs of requests with more than one strip
+    BatchReq req[kMaxBatch];
+};
+
 // Number of FP32 strip partials of a launch.
 int64_t count_strips(const GemmLaunch& g);
 size_t gemm_workspace_bytes(int64_t m, int64_t strips, int64_t k);
 
 hipError_t launch_gemm_stream(const GemmLaunch& g);
+// Streaming-kernel batch: all requests share the tile class (kclass, adtype).
+hipError_t launch_gemm_batch(const BatchArgs& a, int kclass, int adtype, int grid, hipStream_t s);
 hipError_t launch_gemm_mfma(const GemmLaunch& g);
 hipError_t launch_reduce_partials(const float* partials, int S, int64_t m, int64_t k, void* Y,
                                   int y_f64, int64_t ldy, int beta, hipStream_t s);
