@@ -7,10 +7,11 @@ of the paper's 1D layouts emulated on one GPU:
     column blocks of 4096 (strided views of A), partial products summed on the
     device in FP64.
 Each step streams A twice (8 GiB).  value = A bytes / wall time of the timed
-steps (GB/s).  The roofline object covers the streaming kernel: algorithmic
-bytes (A bytes; Omega is generated, never read) per launch / launch duration,
-measured with HIP events that the library records on its launch stream just
-before and after that kernel (sketch_trace_events).
+steps (GB/s), timed with no per-kernel events.  The roofline object covers the
+streaming kernel: algorithmic bytes (A bytes; Omega is generated, never read)
+per launch / launch duration, measured over a second set of the same steps with
+HIP events that the library records on its launch stream just before and after
+that kernel (sketch_trace_events).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -126,18 +127,23 @@ def main():
         step(None)
     torch.cuda.synchronize()
     same = bool(torch.equal(Yrows, Yred))
+    # timed steps (value): no per-kernel events inside, so nothing perturbs them
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t_start.record(stream)
-    for si in range(args.steps):
-        step(si)
+    for _ in range(args.steps):
+        step(None)
     t_end.record(stream)
     torch.cuda.synchronize()
     total_ms = t_start.elapsed_time(t_end)
     ms_step = total_ms / args.steps
     step_bytes = P * share_bytes + red_bytes
     value = step_bytes * args.steps / (total_ms * 1e-3) / 1e9
+    # traced steps (roofline): the library records events around each kernel
+    for si in range(args.steps):
+        step(si)
+    torch.cuda.synchronize()
 
     kern = {"row": [], "col": []}     # streaming-kernel durations (ms) per call
     red = {"row": [], "col": []}      # FP64 reduction-kernel durations

@@ -83,6 +83,12 @@ int sketch_abi_version(void);
 /* Static text for a status code. */
 const char* sketch_status_string(int status);
 
+/* Width (columns of A) of the contraction strips a call with this storage
+ * type and sketch width sums in FP32 before the FP64 strip sum; 0 for
+ * invalid arguments.  The result of a call depends on the strip boundaries
+ * only (never on m, the grid or other launch choices). */
+int64_t sketch_strip_width(int a_dtype, int64_t k);
+
 /* Bytes of device workspace a call needs (0 if none).  The workspace holds
  * the FP32 partial sums of the column strips between the streaming kernel and
  * the FP64 reduction kernel of one call; its contents need no preparation.
@@ -134,9 +140,9 @@ int sketch_gen_matmul(const void* A, int a_dtype, int64_t m, int64_t n, int64_t 
  *   The partial products are summed in FP64 in block order b = 0..P-1 and
  *   rounded once to y_dtype.  Other arguments as for sketch_gen_matmul; the
  *   workspace must hold sketch_workspace_size(1, a_dtype, m, sum n_b, k, P).
- * When each block's width is a multiple of 1024 and row0_b = row0_0 + the
- * block's column offset, the result equals bitwise that of sketch_gen_matmul
- * on the concatenated A.
+ * When each block's width is a multiple of sketch_strip_width(a_dtype, k) and
+ * row0_b = row0_0 + the block's column offset, the result equals bitwise that
+ * of sketch_gen_matmul on the concatenated A.
  */
 int sketch_gen_matmul_reduce(const void* const* A_b, int64_t P, int a_dtype, int64_t m,
                              const int64_t* n_b, const int64_t* lda_b, const int64_t* row0_b,

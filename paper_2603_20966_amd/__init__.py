@@ -59,6 +59,8 @@ def lib() -> ctypes.CDLL:
         L.sketch_status_string.restype = ctypes.c_char_p
         L.sketch_workspace_size.argtypes = [i32, i32, i64, i64, i64, i64]
         L.sketch_workspace_size.restype = sz
+        L.sketch_strip_width.argtypes = [i32, i64]
+        L.sketch_strip_width.restype = i64
         L.sketch_gen_matmul.argtypes = [P, i32, i64, i64, i64, P, u64, i64, i64, i64, P, i32, i64,
                                         i32, P, sz, P]
         L.sketch_gen_matmul_reduce.argtypes = [P, i64, i32, i64, P, P, P, P, u64, i64, i64, P, i32,
@@ -150,6 +152,11 @@ def workspace_for(nbytes: int, device, stream_ptr: int) -> tuple[int, int]:
 # ----------------------------------------------------------------------------
 # ABI calls
 # ----------------------------------------------------------------------------
+def sketch_strip_width(a_dtype: int, k: int) -> int:
+    """Columns per FP32 contraction strip for this storage type and sketch width."""
+    return int(lib().sketch_strip_width(a_dtype, k))
+
+
 def sketch_workspace_size(op: int, a_dtype: int, m: int, n: int, k: int, P: int = 1) -> int:
     return int(lib().sketch_workspace_size(op, a_dtype, m, n, k, P))
 
@@ -293,6 +300,7 @@ def sketch_quantize(A: torch.Tensor, dst: str, *, stream=None):
 
 
 __all__ = ["sketch_abi_version", "sketch_status_string", "sketch_workspace_size",
+           "sketch_strip_width",
            "sketch_gen_matmul", "sketch_gen_matmul_reduce",
            "sketch_gen_omega", "sketch_matmul_omega", "sketch_philox_raw", "sketch_quantize",
            "sketch_trace_events", "SketchError", "lib", "LIB_PATH"]

@@ -108,6 +108,11 @@ const char* sketch_status_string(int status) {
     }
 }
 
+int64_t sketch_strip_width(int a_dtype, int64_t k) {
+    if (!adtype_ok(a_dtype) || k < 1 || k > kMaxK) return 0;
+    return sk::strip_width_for(a_dtype, k);
+}
+
 size_t sketch_workspace_size(int op, int a_dtype, int64_t m, int64_t n, int64_t k, int64_t P) {
     if ((op != 0 && op != 1) || !adtype_ok(a_dtype) || m < 0 || n < 0 || k < 0 || k > kMaxK)
         return 0;

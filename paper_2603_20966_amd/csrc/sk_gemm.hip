@@ -34,9 +34,9 @@
 namespace sk {
 namespace {
 
-constexpr int kLanesPerRow = 16;  // lanes sharing one row segment
-constexpr int kRowGroups = 4;     // row groups per wave pass (4 rows each)
-constexpr int kDepth = 4;         // steps of A loads in flight per wave
+constexpr int kLanesPerRow = 64;  // a whole wave reads one row segment (1 KB per instruction)
+constexpr int kRowGroups = 8;     // rows per wave pass
+constexpr int kDepth = 2;         // steps of A loads in flight per wave
 
 typedef unsigned int v4u32 __attribute__((ext_vector_type(4)));
 
@@ -61,6 +61,8 @@ struct KArgs {
     int S_total;
     int rows_per_wg;
     int num_rb;
+    int64_t tiles;    // strips x row blocks x column groups
+    int64_t tiles8;   // ceil(tiles / 8)
     int y_f64;
     int beta;
     BlockDesc blk[kMaxBlocks];
@@ -171,11 +173,20 @@ struct Tile {
 
 // One tile: issue the first A loads, build the Omega slice in LDS, stream the
 // rows, write the strip partials (or Y).  All threads of the workgroup call it.
+// Sum over all 64 lanes: the 16-lane butterfly, then the four row sums
+// combined pairwise (xor 16, xor 32); every lane receives the same bits.
+__device__ __forceinline__ float wave_sum(float v) {
+    v = row16_sum(v);
+    v += __shfl_xor(v, 16);
+    v += __shfl_xor(v, 32);
+    return v;
+}
+
 template <int K, int ADT, bool GEN>
-__device__ __forceinline__ void tile_body(const Tile& tl, float (*om)[strip_width(K)]) {
+__device__ __forceinline__ void tile_body(const Tile& tl, float (*om)[strip_width(K, ADT)]) {
     constexpr int es = Elem<ADT>::size;
     constexpr int EPL = 16 / es;                 // elements per lane step
-    constexpr int C = strip_width(K);            // columns per strip
+    constexpr int C = strip_width(K, ADT);       // columns per strip
     constexpr int STEP = kLanesPerRow * EPL;     // columns per wave step
     constexpr int T = C / STEP;                  // steps per full strip
     static_assert(C % STEP == 0, "strip must hold whole steps");
@@ -183,23 +194,21 @@ __device__ __forceinline__ void tile_body(const Tile& tl, float (*om)[strip_widt
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int sig = lane & (kLanesPerRow - 1);
-    const int rho = lane >> 4;
     const int kg = tl.kg;
     const int c_base = tl.c_base;
     const int64_t col_begin = tl.col_begin;
     const int w = (int)min<int64_t>(C, tl.n - col_begin);
     const int64_t row_end = tl.row_end;
 
-    // ---- this wave's rows: passes of 16 rows, 64 rows apart -----------------
+    // ---- this wave's rows: passes of 8 rows, 32 rows apart ------------------
     const int64_t lda_bytes = tl.lda * es;
     const bool full = (w == C);
     const int Tr = full ? T : (w + STEP - 1) / STEP;    // steps per pass
-    const int64_t first_pb = tl.row_begin + wave * 16;
+    const int64_t first_pb = tl.row_begin + wave * kRowGroups;
     const int npass = first_pb < row_end ? (int)((row_end - first_pb + kRowQuantum - 1) / kRowQuantum) : 0;
-    const unsigned char* lane_col = tl.A + (col_begin + sig * EPL) * es;
+    const unsigned char* lane_col = tl.A + (col_begin + lane * EPL) * es;
 
-    // Steps run pass by pass (16 rows), column step by column step; loads are
+    // Steps run pass by pass (8 rows), column step by column step; loads are
     // issued kDepth steps ahead of the FMAs that consume them.
     int ip = 0, it_ = 0;   // next step to load: pass, column step
     int cp = 0, ct = 0;    // next step to consume
@@ -212,10 +221,10 @@ __device__ __forceinline__ void tile_body(const Tile& tl, float (*om)[strip_widt
             ++ip;
         }
         const int64_t pb = first_pb + (int64_t)p * kRowQuantum;
-        const int cl = t * STEP + sig * EPL;
+        const int cl = t * STEP + lane * EPL;
 #pragma unroll
         for (int i = 0; i < kRowGroups; ++i) {
-            const int64_t r = min<int64_t>(pb + 4 * i + rho, tl.m - 1);
+            const int64_t r = min<int64_t>(pb + i, tl.m - 1);
             const unsigned char* ptr = lane_col + r * lda_bytes + (int64_t)t * STEP * es;
             if (full || w - cl >= EPL) buf[i] = load_a16(ptr);
             else buf[i] = load_tail<ADT>(ptr, w - cl);
@@ -266,7 +275,7 @@ __device__ __forceinline__ void tile_body(const Tile& tl, float (*om)[strip_widt
     }
     lds_barrier();
 
-    // ---- stream: FMA each step, 16-lane sums at the end of each pass ---------
+    // ---- stream: FMA each step, 64-lane sums at the end of each pass ---------
     float acc[kRowGroups][K];
 #pragma unroll
     for (int i = 0; i < kRowGroups; ++i)
@@ -283,7 +292,7 @@ __device__ __forceinline__ void tile_body(const Tile& tl, float (*om)[strip_widt
         float a[kRowGroups][EPL];
 #pragma unroll
         for (int i = 0; i < kRowGroups; ++i) unpack16<ADT>(raw[i], a[i]);
-        const int cl = t * STEP + sig * EPL;
+        const int cl = t * STEP + lane * EPL;
 #pragma unroll
         for (int c = 0; c < K; ++c) {
             float wv[EPL];
@@ -301,36 +310,47 @@ __device__ __forceinline__ void tile_body(const Tile& tl, float (*om)[strip_widt
                 for (int e = 0; e < EPL; ++e) acc[i][c] = __builtin_fmaf(a[i][e], wv[e], acc[i][c]);
         }
         if (t != Tr - 1) return;
-        // end of pass: row sums and partial (or final) write, then restart
+        // end of pass: row sums, then lane (i, c) of a round writes row i, column c
         const int64_t pb = first_pb + (int64_t)p * kRowQuantum;
 #pragma unroll
-        for (int i = 0; i < kRowGroups; ++i) {
+        for (int i = 0; i < kRowGroups; ++i)
+#pragma unroll
+            for (int c = 0; c < K; ++c) acc[i][c] = wave_sum(acc[i][c]);
+        constexpr int KW = K <= 8 ? 8 : 16;          // lanes per written row
+        constexpr int RPR = 64 / KW;                 // rows written per round
+#pragma unroll
+        for (int q = 0; q < kRowGroups / RPR; ++q) {
+            const int wi = q * RPR + lane / KW;
+            const int wc = lane % KW;
             float mine = 0.0f;
 #pragma unroll
-            for (int c = 0; c < K; ++c) {
-                const float sum = row16_sum(acc[i][c]);
-                if (sig == c) mine = sum;
-                acc[i][c] = 0.0f;
-            }
-            const int64_t r = pb + 4 * i + rho;
-            if (r < row_end && sig < kg) {
+            for (int i = q * RPR; i < (q + 1) * RPR; ++i)
+#pragma unroll
+                for (int c = 0; c < K; ++c)
+                    if (wi == i && wc == c) mine = acc[i][c];
+            const int64_t r = pb + wi;
+            if (r < row_end && wc < kg) {
                 if (tl.scales) mine *= tl.scales[r >> 7];
                 if (tl.single) {
                     double y = (double)mine;
                     if (tl.y_f64) {
-                        double* Yp = static_cast<double*>(tl.Y) + r * tl.ldy + c_base + sig;
+                        double* Yp = static_cast<double*>(tl.Y) + r * tl.ldy + c_base + wc;
                         if (tl.beta) y += *Yp;
                         *Yp = y;
                     } else {
-                        float* Yp = static_cast<float*>(tl.Y) + r * tl.ldy + c_base + sig;
+                        float* Yp = static_cast<float*>(tl.Y) + r * tl.ldy + c_base + wc;
                         if (tl.beta) y += (double)*Yp;
                         *Yp = (float)y;
                     }
                 } else {
-                    tl.partials[(tl.strip_index * tl.m + r) * tl.k + c_base + sig] = mine;
+                    tl.partials[(tl.strip_index * tl.m + r) * tl.k + c_base + wc] = mine;
                 }
             }
         }
+#pragma unroll
+        for (int i = 0; i < kRowGroups; ++i)
+#pragma unroll
+            for (int c = 0; c < K; ++c) acc[i][c] = 0.0f;
     };
 
     while (cp < npass) {
@@ -346,11 +366,24 @@ __device__ __forceinline__ void tile_body(const Tile& tl, float (*om)[strip_widt
 
 // One call: grid (strips of all blocks, row blocks, column groups), one tile
 // per workgroup; the blocks share the output (contraction split).
+// Tile of a workgroup in an XCD-grouped order: workgroups are handed to the 8
+// XCDs round-robin, so XCD x receives ids x, x+8, ...; giving it the
+// contiguous tile range [x*T8, (x+1)*T8) (strips fastest, then row blocks)
+// makes each XCD stream whole rows of A at a time.
+__device__ __forceinline__ int64_t xcd_tile(int64_t id, int64_t T8) {
+    return (id % 8) * T8 + id / 8;
+}
+
 template <int K, int ADT, bool GEN>
 __global__ __launch_bounds__(kWgThreads) void k_gemm_stream(const KArgs args) {
-    constexpr int C = strip_width(K);
+    constexpr int C = strip_width(K, ADT);
     __shared__ float om[K][C];
-    const int strip = blockIdx.x;
+    const int64_t t = xcd_tile(blockIdx.x, args.tiles8);
+    if (t >= args.tiles) return;
+    const int strip = (int)(t % args.S_total);
+    const int64_t rbt = t / args.S_total;
+    const int rb = (int)(rbt % args.num_rb);
+    const int cg = (int)(rbt / args.num_rb);
     int b = 0;
     int64_t strip_in_block = strip;
     for (; b < args.P; ++b) {
@@ -368,9 +401,9 @@ __global__ __launch_bounds__(kWgThreads) void k_gemm_stream(const KArgs args) {
     tl.m = args.m;
     tl.k = args.k;
     tl.col_begin = strip_in_block * C;
-    tl.row_begin = (int64_t)blockIdx.y * args.rows_per_wg;
+    tl.row_begin = (int64_t)rb * args.rows_per_wg;
     tl.row_end = min<int64_t>(tl.row_begin + args.rows_per_wg, args.m);
-    tl.c_base = blockIdx.z * kColGroup;
+    tl.c_base = cg * kColGroup;
     tl.kg = (int)min<int64_t>(kColGroup, args.k - tl.c_base);
     tl.key0 = args.key0;
     tl.key1 = args.key1;
@@ -392,10 +425,13 @@ __global__ __launch_bounds__(kWgThreads) void k_gemm_stream(const KArgs args) {
 // output and partial array, so its result does not depend on the batch.
 template <int K, int ADT>
 __global__ __launch_bounds__(kWgThreads) void k_gemm_batch(const BatchArgs args) {
-    constexpr int C = strip_width(K);
+    constexpr int C = strip_width(K, ADT);
     __shared__ float om[K][C];
     bool first = true;
-    for (int64_t t = blockIdx.x; t < args.total_tiles; t += gridDim.x) {
+    const int64_t T8 = (args.total_tiles + 7) / 8;
+    for (int64_t v = blockIdx.x; v < 8 * T8; v += gridDim.x) {   // gridDim.x is a multiple of 8
+        const int64_t t = xcd_tile(v, T8);
+        if (t >= args.total_tiles) continue;
         int q = 0;
         while (q + 1 < args.count && t >= args.req[q + 1].tile_begin) ++q;
         const BatchReq& rq = args.req[q];
@@ -531,7 +567,7 @@ int wg_target() {
     static int t = [] {
         const char* e = getenv("SKETCH_WG_TARGET");
         int v = e ? atoi(e) : 0;
-        return v > 0 ? v : 1024;
+        return v > 0 ? v : 256;
     }();
     return t;
 }
@@ -577,14 +613,16 @@ hipError_t launch_gemm_stream(const GemmLaunch& g) {
     a.y_f64 = g.y_f64;
     a.beta = g.beta;
     for (int b = 0; b < g.P; ++b) a.blk[b] = g.blk[b];
-    // rows per workgroup: a multiple of 64 giving about wg_target() workgroups
+    // rows per workgroup: a multiple of 32 giving about wg_target() tiles
     int64_t R = (g.m * S * ncg) / wg_target();
     R = std::max<int64_t>(kRowQuantum, std::min<int64_t>(1024, (R / kRowQuantum) * kRowQuantum));
     const int64_t nrb = (g.m + R - 1) / R;
     a.rows_per_wg = (int)R;
     a.num_rb = (int)nrb;
+    a.tiles = S * nrb * ncg;
+    a.tiles8 = (a.tiles + 7) / 8;
     if (S > 1) a.partials = static_cast<float*>(g.workspace);
-    dim3 grid((unsigned)S, (unsigned)nrb, (unsigned)ncg);
+    dim3 grid((unsigned)(8 * a.tiles8));
     const bool gen = (g.omega == nullptr);
     const TraceEvents& tr = g.trace;
     switch (g.adtype) {
@@ -597,6 +635,7 @@ hipError_t launch_gemm_stream(const GemmLaunch& g) {
 hipError_t launch_gemm_batch(const BatchArgs& a, int kclass, int adtype, int grid,
                              hipStream_t s) {
     if (a.count == 0 || a.total_tiles == 0) return hipSuccess;
+    grid = std::max(8, (grid + 7) / 8 * 8);   // the tile walk assumes a multiple of 8
     const dim3 g((unsigned)grid), blk(kWgThreads);
 #define SK_BATCH(KK)                                                                       \
     case KK:                                                                               \

@@ -11,16 +11,23 @@ namespace sk {
 constexpr int kMaxBlocks = 64;     // contraction blocks per reduce call
 constexpr int kColGroup = 16;      // Omega columns handled by one workgroup
 constexpr int kWgThreads = 256;    // threads per workgroup of the streaming kernel
-constexpr int kRowQuantum = 64;    // rows per workgroup pass (4 waves x 16 rows)
+constexpr int kRowQuantum = 32;    // rows per workgroup pass (4 waves x 8 rows)
 
 // Register-tile class (template K of the streaming kernel) for a group of
 // kg Omega columns.
 constexpr int k_class(int kg) { return kg <= 6 ? kg : kg <= 8 ? 8 : kg <= 12 ? 12 : 16; }
 
-// Strip width (columns of A per workgroup, and per FP32 partial sum).  A
-// function of the tile class only, so results never depend on m or on the
-// launch shape.
-constexpr int strip_width(int kclass) { return kclass <= 8 ? 1024 : 512; }
+// Strip width (columns of A per workgroup, and per FP32 partial sum) of the
+// streaming kernel.  A function of the tile class and the storage type only,
+// so results never depend on m or on the launch shape.  It holds whole wave
+// steps (64 lanes x 16 bytes) and keeps the Omega slice (kclass x width
+// floats) within 64 KiB of LDS; narrower types get wider strips so the
+// 64-lane sums stay amortised over as many elements.
+constexpr int strip_width(int kclass, int adtype) {
+    return adtype == 0 ? (kclass <= 8 ? 1024 : 512)
+         : adtype == 1 ? (kclass <= 8 ? 2048 : 1024)
+                       : (kclass <= 4 ? 4096 : kclass <= 8 ? 2048 : 1024);
+}
 
 // The matrix-core kernel takes FP32 A with a sketch wider than one column
 // group; its strips are 2048 columns.
@@ -30,7 +37,7 @@ constexpr bool use_mfma(int adtype, int64_t k) { return adtype == 0 && k > kColG
 // Strip width used for a sketch of width k with A stored as adtype.
 constexpr int64_t strip_width_for(int adtype, int64_t k) {
     return use_mfma(adtype, k) ? kMfmaStrip
-                               : strip_width(k_class((int)(k < kColGroup ? k : kColGroup)));
+                               : strip_width(k_class((int)(k < kColGroup ? k : kColGroup)), adtype);
 }
 
 struct BlockDesc {
