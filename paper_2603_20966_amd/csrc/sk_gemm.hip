@@ -173,15 +173,6 @@ struct Tile {
 
 // One tile: issue the first A loads, build the Omega slice in LDS, stream the
 // rows, write the strip partials (or Y).  All threads of the workgroup call it.
-// Sum over all 64 lanes: the 16-lane butterfly, then the four row sums
-// combined pairwise (xor 16, xor 32); every lane receives the same bits.
-__device__ __forceinline__ float wave_sum(float v) {
-    v = row16_sum(v);
-    v += __shfl_xor(v, 16);
-    v += __shfl_xor(v, 32);
-    return v;
-}
-
 template <int K, int ADT, bool GEN>
 __device__ __forceinline__ void tile_body(const Tile& tl, float (*om)[strip_width(K, ADT)]) {
     constexpr int es = Elem<ADT>::size;
@@ -310,26 +301,46 @@ __device__ __forceinline__ void tile_body(const Tile& tl, float (*om)[strip_widt
                 for (int e = 0; e < EPL; ++e) acc[i][c] = __builtin_fmaf(a[i][e], wv[e], acc[i][c]);
         }
         if (t != Tr - 1) return;
-        // end of pass: row sums, then lane (i, c) of a round writes row i, column c
+        // End of pass: sum each of the V = 8K accumulators over the 64 lanes as a
+        // reduce-scatter.  permlane32_swap exchanges rows {2,3} of one register
+        // with rows {0,1} of another, so one swap + add halves the values per
+        // lane (lanes 0-31 keep the first half, lanes 32-63 the second);
+        // permlane16_swap does the same between rows 0|1 and 2|3; a 4-stage DPP
+        // butterfly finishes each value inside its 16-lane row.  Row r then
+        // holds values [r*V/4, (r+1)*V/4); every addition order is fixed.
         const int64_t pb = first_pb + (int64_t)p * kRowQuantum;
+        constexpr int V = kRowGroups * K;
+        constexpr int H = V / 2;
+        constexpr int Q = V / 4;
+        float hv[H];
 #pragma unroll
-        for (int i = 0; i < kRowGroups; ++i)
+        for (int j = 0; j < H; ++j) {
+            const int i0 = j / K, c0 = j % K, i1 = (j + H) / K, c1 = (j + H) % K;
+            const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(acc[i0][c0]),
+                                                             __float_as_uint(acc[i1][c1]), false, false);
+            hv[j] = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
+        }
+        float qv[Q];
 #pragma unroll
-            for (int c = 0; c < K; ++c) acc[i][c] = wave_sum(acc[i][c]);
-        constexpr int KW = K <= 8 ? 8 : 16;          // lanes per written row
-        constexpr int RPR = 64 / KW;                 // rows written per round
+        for (int j = 0; j < Q; ++j) {
+            const auto sw = __builtin_amdgcn_permlane16_swap(__float_as_uint(hv[j]),
+                                                             __float_as_uint(hv[j + Q]), false, false);
+            qv[j] = row16_sum(__uint_as_float(sw[0]) + __uint_as_float(sw[1]));
+        }
+        const int row16 = lane >> 4;
+        const int vbase = (row16 >> 1) * H + (row16 & 1) * Q;
+        const int sig = lane & 15;
 #pragma unroll
-        for (int q = 0; q < kRowGroups / RPR; ++q) {
-            const int wi = q * RPR + lane / KW;
-            const int wc = lane % KW;
+        for (int base = 0; base < Q; base += 16) {
             float mine = 0.0f;
 #pragma unroll
-            for (int i = q * RPR; i < (q + 1) * RPR; ++i)
-#pragma unroll
-                for (int c = 0; c < K; ++c)
-                    if (wi == i && wc == c) mine = acc[i][c];
+            for (int j = base; j < base + 16 && j < Q; ++j)
+                if (sig == j - base) mine = qv[j];
+            const int v = vbase + base + sig;        // accumulator index i*K + c
+            const int wi = v / K;
+            const int wc = v - wi * K;
             const int64_t r = pb + wi;
-            if (r < row_end && wc < kg) {
+            if (base + sig < Q && r < row_end && wc < kg) {
                 if (tl.scales) mine *= tl.scales[r >> 7];
                 if (tl.single) {
                     double y = (double)mine;

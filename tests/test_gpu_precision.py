@@ -94,11 +94,13 @@ def test_fp8_product(m, n, k, row0):
 
 
 def test_low_precision_reduce_layout_matches_row_layout():
-    """1Dred over BF16 / FP8 column blocks equals the row layout bitwise."""
-    m, n, P = 256, 4096, 4
-    A = normal_matrix(m, n, seed=77)
-    w = n // P
-    for kind in ("bf16", "fp8"):
+    """1Dred over BF16 / FP8 column blocks equals the row layout bitwise when the
+    blocks are whole strips (sketch_strip_width)."""
+    P = 4
+    for kind, code in (("bf16", 1), ("fp8", 2)):
+        w = sk.sketch_strip_width(code, 5)
+        m, n = 256, P * w
+        A = normal_matrix(m, n, seed=77)
         Aq, sc = sk.sketch_quantize(dev_f32(A), kind)
         Yrow = sk.sketch_gen_matmul(Aq, 3, 5, a_scales=sc)
         blocks = [Aq[:, b * w:(b + 1) * w] for b in range(P)]
