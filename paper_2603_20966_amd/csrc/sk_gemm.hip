@@ -482,7 +482,7 @@ __global__ __launch_bounds__(kWgThreads) void k_gemm_batch(const BatchArgs args)
 }
 
 // Y (=|+=) sum over strips of the FP32 partials, in FP64, strip order fixed;
-// one thread per output element, loads issued 16 at a time.
+// one thread per output element, loads issued 32 at a time.
 __global__ void k_reduce_partials(const float* __restrict__ partials, int S, int64_t m, int64_t k,
                                   void* Y, int y_f64, int64_t ldy, int beta) {
     const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -493,12 +493,12 @@ __global__ void k_reduce_partials(const float* __restrict__ partials, int S, int
     const int64_t sstride = m * k;
     double y = 0.0;
     int s = 0;
-    for (; s + 16 <= S; s += 16) {
-        float v[16];
+    for (; s + 32 <= S; s += 32) {
+        float v[32];
 #pragma unroll
-        for (int j = 0; j < 16; ++j) v[j] = __builtin_nontemporal_load(p + (int64_t)(s + j) * sstride);
+        for (int j = 0; j < 32; ++j) v[j] = __builtin_nontemporal_load(p + (int64_t)(s + j) * sstride);
 #pragma unroll
-        for (int j = 0; j < 16; ++j) y += (double)v[j];
+        for (int j = 0; j < 32; ++j) y += (double)v[j];
     }
     for (; s < S; ++s) y += (double)p[(int64_t)s * sstride];
     if (y_f64) {
@@ -574,13 +574,62 @@ hipError_t dispatch_k(int kc, const KArgs& a, dim3 grid, hipStream_t s, const Tr
     }
 }
 
-int wg_target() {
-    static int t = [] {
-        const char* e = getenv("SKETCH_WG_TARGET");
-        int v = e ? atoi(e) : 0;
-        return v > 0 ? v : 256;
+// Resident workgroups of one streaming-kernel instance on the current device
+// (occupancy x compute units), cached per (device, kernel).
+template <int K, int ADT, bool GEN>
+int resident_slots() {
+    static int slots[64] = {0};
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    if (dev < 0 || dev >= 64) dev = 0;
+    if (slots[dev] == 0) {
+        int per_cu = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gemm_stream<K, ADT, GEN>,
+                                                         kWgThreads, 0) != hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            cus < 1)
+            cus = 256;
+        slots[dev] = per_cu * cus;
+    }
+    return slots[dev];
+}
+
+// Rows per tile: the smallest multiple of 32 for which all tiles are resident
+// at once (one round, balanced to within one 32-row pass).  Never below
+// 32 rows; an environment override (SKETCH_ROWS_PER_TILE) exists for tuning.
+int64_t rows_per_tile(int64_t m, int64_t strips, int64_t ncg, int slots) {
+    static const int64_t forced = [] {
+        const char* e = getenv("SKETCH_ROWS_PER_TILE");
+        const long long v = e ? atoll(e) : 0;
+        return (int64_t)(v > 0 ? v : 0);
     }();
-    return t;
+    int64_t R = forced > 0 ? forced
+                           : (m * strips * ncg + slots - 1) / std::max<int64_t>(1, slots);
+    R = std::max<int64_t>(kRowQuantum, (R + kRowQuantum - 1) / kRowQuantum * kRowQuantum);
+    return R;
+}
+
+template <int ADT, bool GEN>
+int slots_for(int kc) {
+    switch (kc) {
+    case 1: return resident_slots<1, ADT, GEN>();
+    case 2: return resident_slots<2, ADT, GEN>();
+    case 3: return resident_slots<3, ADT, GEN>();
+    case 4: return resident_slots<4, ADT, GEN>();
+    case 5: return resident_slots<5, ADT, GEN>();
+    case 6: return resident_slots<6, ADT, GEN>();
+    case 8: return resident_slots<8, ADT, GEN>();
+    case 12: return resident_slots<12, ADT, GEN>();
+    default: return resident_slots<16, ADT, GEN>();
+    }
+}
+
+int kernel_slots(int adtype, bool gen, int kc) {
+    if (adtype == 0) return gen ? slots_for<0, true>(kc) : slots_for<0, false>(kc);
+    if (adtype == 1) return gen ? slots_for<1, true>(kc) : slots_for<1, false>(kc);
+    return gen ? slots_for<2, true>(kc) : slots_for<2, false>(kc);
 }
 
 }  // namespace
@@ -624,9 +673,8 @@ hipError_t launch_gemm_stream(const GemmLaunch& g) {
     a.y_f64 = g.y_f64;
     a.beta = g.beta;
     for (int b = 0; b < g.P; ++b) a.blk[b] = g.blk[b];
-    // rows per workgroup: a multiple of 32 giving about wg_target() tiles
-    int64_t R = (g.m * S * ncg) / wg_target();
-    R = std::max<int64_t>(kRowQuantum, std::min<int64_t>(1024, (R / kRowQuantum) * kRowQuantum));
+    const bool gen = (g.omega == nullptr);
+    const int64_t R = rows_per_tile(g.m, S, ncg, kernel_slots(g.adtype, gen, kc));
     const int64_t nrb = (g.m + R - 1) / R;
     a.rows_per_wg = (int)R;
     a.num_rb = (int)nrb;
@@ -634,7 +682,6 @@ hipError_t launch_gemm_stream(const GemmLaunch& g) {
     a.tiles8 = (a.tiles + 7) / 8;
     if (S > 1) a.partials = static_cast<float*>(g.workspace);
     dim3 grid((unsigned)(8 * a.tiles8));
-    const bool gen = (g.omega == nullptr);
     const TraceEvents& tr = g.trace;
     switch (g.adtype) {
     case 0: return gen ? dispatch_k<0, true>(kc, a, grid, g.stream, tr) : dispatch_k<0, false>(kc, a, grid, g.stream, tr);
