@@ -574,62 +574,36 @@ hipError_t dispatch_k(int kc, const KArgs& a, dim3 grid, hipStream_t s, const Tr
     }
 }
 
-// Resident workgroups of one streaming-kernel instance on the current device
-// (occupancy x compute units), cached per (device, kernel).
-template <int K, int ADT, bool GEN>
-int resident_slots() {
-    static int slots[64] = {0};
+// Compute units of the current device (cached per device).
+int device_cus() {
+    static int cus[64] = {0};
     int dev = 0;
     (void)hipGetDevice(&dev);
     if (dev < 0 || dev >= 64) dev = 0;
-    if (slots[dev] == 0) {
-        int per_cu = 0, cus = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gemm_stream<K, ADT, GEN>,
-                                                         kWgThreads, 0) != hipSuccess ||
-            per_cu < 1)
-            per_cu = 1;
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            cus < 1)
-            cus = 256;
-        slots[dev] = per_cu * cus;
+    if (cus[dev] == 0) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            n < 1)
+            n = 256;
+        cus[dev] = n;
     }
-    return slots[dev];
+    return cus[dev];
 }
 
-// Rows per tile: the smallest multiple of 32 for which all tiles are resident
-// at once (one round, balanced to within one 32-row pass).  Never below
-// 32 rows; an environment override (SKETCH_ROWS_PER_TILE) exists for tuning.
-int64_t rows_per_tile(int64_t m, int64_t strips, int64_t ncg, int slots) {
+// Rows per tile: a multiple of 32 giving about two tiles per compute unit,
+// at most 512 rows (measured best on the 4096 x 32768 share and on the
+// 32768 x 32768 column layout).  SKETCH_ROWS_PER_TILE overrides it for tuning.
+int64_t rows_per_tile(int64_t m, int64_t strips, int64_t ncg) {
     static const int64_t forced = [] {
         const char* e = getenv("SKETCH_ROWS_PER_TILE");
         const long long v = e ? atoll(e) : 0;
         return (int64_t)(v > 0 ? v : 0);
     }();
-    int64_t R = forced > 0 ? forced
-                           : (m * strips * ncg + slots - 1) / std::max<int64_t>(1, slots);
-    R = std::max<int64_t>(kRowQuantum, (R + kRowQuantum - 1) / kRowQuantum * kRowQuantum);
-    return R;
-}
-
-template <int ADT, bool GEN>
-int slots_for(int kc) {
-    switch (kc) {
-    case 1: return resident_slots<1, ADT, GEN>();
-    case 2: return resident_slots<2, ADT, GEN>();
-    case 3: return resident_slots<3, ADT, GEN>();
-    case 4: return resident_slots<4, ADT, GEN>();
-    case 5: return resident_slots<5, ADT, GEN>();
-    case 6: return resident_slots<6, ADT, GEN>();
-    case 8: return resident_slots<8, ADT, GEN>();
-    case 12: return resident_slots<12, ADT, GEN>();
-    default: return resident_slots<16, ADT, GEN>();
-    }
-}
-
-int kernel_slots(int adtype, bool gen, int kc) {
-    if (adtype == 0) return gen ? slots_for<0, true>(kc) : slots_for<0, false>(kc);
-    if (adtype == 1) return gen ? slots_for<1, true>(kc) : slots_for<1, false>(kc);
-    return gen ? slots_for<2, true>(kc) : slots_for<2, false>(kc);
+    const int64_t want = 2 * (int64_t)device_cus();
+    int64_t R = forced > 0 ? forced : (m * strips * ncg + want - 1) / want;
+    R = (R + kRowQuantum - 1) / kRowQuantum * kRowQuantum;
+    if (forced == 0) R = std::min<int64_t>(R, 512);
+    return std::max<int64_t>(kRowQuantum, R);
 }
 
 }  // namespace
@@ -674,7 +648,7 @@ hipError_t launch_gemm_stream(const GemmLaunch& g) {
     a.beta = g.beta;
     for (int b = 0; b < g.P; ++b) a.blk[b] = g.blk[b];
     const bool gen = (g.omega == nullptr);
-    const int64_t R = rows_per_tile(g.m, S, ncg, kernel_slots(g.adtype, gen, kc));
+    const int64_t R = rows_per_tile(g.m, S, ncg);
     const int64_t nrb = (g.m + R - 1) / R;
     a.rows_per_wg = (int)R;
     a.num_rb = (int)nrb;
