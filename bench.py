@@ -27,6 +27,28 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_gemm_stream_k5_f32.json")
+KERNEL_SOURCES = ("paper_2603_20966_amd/csrc/sk_gemm.hip", "paper_2603_20966_amd/csrc/sk_device.hpp",
+                  "paper_2603_20966_amd/csrc/sk_internal.hpp")
+
+
+def measured_traffic(n_row, n_col):
+    """HBM bytes per launch of the streaming kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE passes (scaled by a plain copy of known size), averaged
+    over this step's launches; None when the kernel sources changed since."""
+    import hashlib
+
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if h.hexdigest() != rec.get("kernel_sources_sha256"):
+        return None
+    pl = rec["per_launch"]
+    return (n_row * pl["row"]["traffic_bytes"] + n_col * pl["col"]["traffic_bytes"]) / (n_row + n_col)
 METRIC = "A-stream GB/s (% HBM peak) for Y=A·Ω(seed) at k=5; p50/p99 latency served"
 
 
@@ -183,7 +205,7 @@ def main():
                    "m": N, "n": N, "k": k, "P": P, "bytes_per_step": step_bytes},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                     "traffic": None,
+                     "traffic": measured_traffic(P, 1),
                      "kernel": "k_gemm_stream<5, f32, generated Omega>",
                      "bytes_per_launch": "536870912 (row share) / 4294967296 (column layout)",
                      "launches": n_launch,
