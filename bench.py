@@ -58,6 +58,9 @@ def parse():
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--workload", default="shares", choices=["shares", "ksweep", "precision"],
+                   help="shares: the headline step (default); ksweep: 65536x16384, k in "
+                        "{5,16,64,256}, generated vs stored Omega; precision: BF16 / FP8 A")
     p.add_argument("--copy-calibration", action="store_true",
                    help="also run a plain 1 GiB device copy (known traffic) for counter scaling")
     p.add_argument("--cpu-seconds", type=float, default=10.0,
@@ -98,6 +101,107 @@ def cpu_baseline(A, P, k, seed, target_s):
                       f"{N}x{N} A, k={k}) repeated {reps}x, {dt:.1f} s wall"}
 
 
+def _timeit(torch, stream, fn, reps, warmup=2):
+    """Median and minimum of reps timed calls (HIP events on the launch stream), in ms."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    evs = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        evs.append((e0, e1))
+    torch.cuda.synchronize()
+    ts = sorted(a.elapsed_time(b) for a, b in evs)
+    return ts[len(ts) // 2], ts[0]
+
+
+def run_ksweep(args):
+    """65536 x 16384 FP32 A, k in {5, 16, 64, 256}: the generated operand (one call) against
+    the stored operand (Omega materialised in HBM by sketch_gen_omega, then read by
+    sketch_matmul_omega), i.e. Gen vs Comm of Sec. 6.3 on one device."""
+    import torch
+
+    import paper_2603_20966_amd as sk
+    from sketch_inputs import normal_matrix_device
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    m, n = 65536, 16384
+    A = normal_matrix_device(m, n, seed=0, device=dev)
+    rows = []
+    for k in (5, 16, 64, 256):
+        Y = torch.empty((m, k), device=dev)
+        Om = torch.empty((n, k), device=dev)
+        t_gen, t_gen_min = _timeit(torch, stream, lambda: sk.sketch_gen_matmul(A, 1, k, Y=Y,
+                                                                               stream=stream),
+                                   args.steps)
+        t_fill, _ = _timeit(torch, stream, lambda: sk.sketch_gen_omega(1, 0, n, 0, k, out=Om,
+                                                                       stream=stream), args.steps)
+        t_mm, _ = _timeit(torch, stream, lambda: sk.sketch_matmul_omega(A, Om, Y=Y, stream=stream),
+                          args.steps)
+        bytes_a = m * n * 4
+        flops = 2 * m * n * k
+        kern = "matrix cores (v_mfma_f32_16x16x4f32)" if k > 16 else "VALU FMA"
+        bound = "hbm" if k <= 16 else "mfma_fp32"
+        peak = HBM_PEAK_GBPS if bound == "hbm" else 157.3
+        achieved = bytes_a / (t_gen * 1e-3) / 1e9 if bound == "hbm" else flops / (t_gen * 1e-3) / 1e12
+        rows.append({"k": k, "kernel": kern, "gen_ms": round(t_gen, 4), "gen_min_ms": round(t_gen_min, 4),
+                     "gen_GBps": round(bytes_a / (t_gen * 1e-3) / 1e9, 1),
+                     "gen_TFLOPs": round(flops / (t_gen * 1e-3) / 1e12, 2),
+                     "roofline": {"bound": bound, "achieved": round(achieved, 2), "peak": peak,
+                                  "unit": "GB/s" if bound == "hbm" else "TFLOP/s",
+                                  "frac": round(achieved / peak, 4)},
+                     "stored_fill_ms": round(t_fill, 4), "stored_matmul_ms": round(t_mm, 4),
+                     "stored_total_ms": round(t_fill + t_mm, 4),
+                     "gen_speedup_vs_stored": round((t_fill + t_mm) / t_gen, 3)})
+    out = {"metric": "Y=A*Omega(seed) time per call, 65536x16384 FP32 A, k sweep; generated vs "
+                     "stored Omega", "unit": "ms", "n_gpus": 1, "steps": args.steps,
+           "higher_is_better": False, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "A 65536x16384 fp32 N(0,1), k in {5,16,64,256}"}, "rows": rows}
+    print(json.dumps(out), flush=True)
+
+
+def run_precision(args):
+    """A 32768 x 32768 stored as BF16 and as FP8-E4M3 (per-128-row scales); k = 5 and 64.
+    Quantisation is preprocessing (untimed).  Rate = bytes of the stored A / call time."""
+    import torch
+
+    import paper_2603_20966_amd as sk
+    from sketch_inputs import normal_matrix_device
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    N = 32768
+    A = normal_matrix_device(N, N, seed=0, device=dev)
+    rows = []
+    for k in (5, 64):
+        Y = torch.empty((N, k), device=dev)
+        t32, _ = _timeit(torch, stream, lambda: sk.sketch_gen_matmul(A, 1, k, Y=Y, stream=stream),
+                         args.steps)
+        rows.append({"a_dtype": "f32", "k": k, "ms": round(t32, 4),
+                     "A_GBps": round(N * N * 4 / (t32 * 1e-3) / 1e9, 1)})
+    for kind, esz in (("bf16", 2), ("fp8", 1)):
+        Aq, sc = sk.sketch_quantize(A, kind, stream=stream)
+        torch.cuda.synchronize()
+        for k in (5, 64):
+            Y = torch.empty((N, k), device=dev)
+            t, _ = _timeit(torch, stream, lambda: sk.sketch_gen_matmul(Aq, 1, k, Y=Y, a_scales=sc,
+                                                                       stream=stream), args.steps)
+            rows.append({"a_dtype": kind, "k": k, "ms": round(t, 4),
+                         "A_GBps": round(N * N * esz / (t * 1e-3) / 1e9, 1),
+                         "frac_hbm": round(N * N * esz / (t * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)})
+        del Aq
+    out = {"metric": "A-stream GB/s, Y=A*Omega(seed), A stored in FP32 / BF16 / FP8-E4M3",
+           "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "higher_is_better": True,
+           "dtype": "bf16/fp8 storage, f32 accumulate", "data": "synthetic",
+           "config": {"workload": "A 32768x32768 N(0,1), k in {5, 64}"}, "rows": rows}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -105,6 +209,11 @@ def main():
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
     import torch
+
+    if args.workload == "ksweep":
+        return run_ksweep(args)
+    if args.workload == "precision":
+        return run_precision(args)
 
     import paper_2603_20966_amd as sk
     from sketch_inputs import normal_matrix_device
