@@ -29,10 +29,12 @@ constexpr int strip_width(int kclass, int adtype) {
                        : (kclass <= 4 ? 4096 : kclass <= 8 ? 2048 : 1024);
 }
 
-// The matrix-core kernel takes FP32 A with a sketch wider than one column
-// group; its strips are 2048 columns.
+// The matrix-core kernel takes FP32 A once k > 8: past that the VALU path
+// spends more than half its issue slots on FMAs at HBM speed (measured at
+// k = 16: 4.1 TB/s on VALU).  Its strips are 2048 columns.
 constexpr int kMfmaStrip = 2048;
-constexpr bool use_mfma(int adtype, int64_t k) { return adtype == 0 && k > kColGroup; }
+constexpr int kMfmaMinK = 9;
+constexpr bool use_mfma(int adtype, int64_t k) { return adtype == 0 && k >= kMfmaMinK; }
 
 // Strip width used for a sketch of width k with A stored as adtype.
 constexpr int64_t strip_width_for(int adtype, int64_t k) {

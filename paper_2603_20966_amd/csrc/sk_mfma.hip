@@ -1,8 +1,10 @@
-// Matrix-core kernel for Y = A * Omega(seed) with a wide sketch (k > 16) on gfx950.
+// Matrix-core kernel for Y = A * Omega(seed) with a wide sketch (k > 8) on gfx950.
 //
-// Once k is large the product is a dense contraction (2k flops per A element,
-// past the FP32 ridge at k ~ 20), so the local multiplication of Alg. 1 runs on
-// the MFMA units: v_mfma_f32_16x16x4f32, FP32 in, FP32 accumulate.
+// Once k is large the product is a dense contraction (2k flops per A element;
+// non-packed FP32 VALU FMAs reach their ridge near k = 20, and above k ~ 8
+// they already take most issue slots at HBM speed), so the local
+// multiplication of Alg. 1 runs on the MFMA units: v_mfma_f32_16x16x4f32,
+// FP32 in, FP32 accumulate.
 //
 // Tile of one workgroup (256 threads = 4 waves): 256 rows of A x a strip of
 // kMfmaStrip contraction columns x BN = 16*NT sketch columns.  Each wave owns
@@ -244,6 +246,7 @@ hipError_t launch_m(const MArgs& a, dim3 grid, hipStream_t s) {
 template <bool GEN>
 hipError_t dispatch_m(int nt, const MArgs& a, dim3 grid, hipStream_t s) {
     switch (nt) {
+    case 1: return launch_m<1, GEN>(a, grid, s);
     case 2: return launch_m<2, GEN>(a, grid, s);
     case 4: return launch_m<4, GEN>(a, grid, s);
     default: return launch_m<8, GEN>(a, grid, s);
@@ -253,7 +256,7 @@ hipError_t dispatch_m(int nt, const MArgs& a, dim3 grid, hipStream_t s) {
 }  // namespace
 
 // N-tiles (of 16 sketch columns) per workgroup for a sketch of width k.
-int mfma_ntiles(int64_t k) { return k <= 32 ? 2 : k <= 64 ? 4 : 8; }
+int mfma_ntiles(int64_t k) { return k <= 16 ? 1 : k <= 32 ? 2 : k <= 64 ? 4 : 8; }
 
 hipError_t launch_gemm_mfma(const GemmLaunch& g) {
     const int nt = mfma_ntiles(g.k);

@@ -139,8 +139,10 @@ def test_workspace_size_rules():
     assert b >= (32 + 8) * 32768 * 5 * 4                # bound valid for any 8-way split
     assert ws(2, F32, 1, 1, 1, 1) == 0 and ws(0, 5, 1, 1, 1, 1) == 0 and ws(1, F32, 1, 1, 1, 0) == 0
     assert ws(0, F32, 100, 5000, 300, 1) == 0           # k > 256 is invalid
-    # a wider sketch uses narrower strips
-    assert ws(0, F32, 4096, 32768, 16, 1) >= 64 * 4096 * 16 * 4
+    # matrix-core path (FP32, k > 8): 2048-column strips
+    assert ws(0, F32, 4096, 32768, 16, 1) == 16 * 4096 * 16 * 4
+    assert sk.sketch_strip_width(F32, 5) == 1024 and sk.sketch_strip_width(F32, 9) == 2048
+    assert sk.sketch_strip_width(BF16, 5) == 2048 and sk.sketch_strip_width(FP8, 4) == 4096
 
 
 def test_python_binding_requires_library(monkeypatch, tmp_path):
