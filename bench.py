@@ -58,9 +58,17 @@ def parse():
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--workload", default="shares", choices=["shares", "ksweep", "precision"],
+    p.add_argument("--workload", default="shares",
+                   choices=["shares", "ksweep", "precision", "serve"],
                    help="shares: the headline step (default); ksweep: 65536x16384, k in "
-                        "{5,16,64,256}, generated vs stored Omega; precision: BF16 / FP8 A")
+                        "{5,16,64,256}, generated vs stored Omega; precision: BF16 / FP8 A; "
+                        "serve: Poisson stream of uneven requests through the request server")
+    p.add_argument("--serve-requests", type=int, default=2000,
+                   help="requests of the served stream (also summarised in the default line)")
+    p.add_argument("--serve-slots", type=int, default=32, help="server in-flight slots")
+    p.add_argument("--serve-budget-gib", type=float, default=64.0, help="server memory budget")
+    p.add_argument("--no-serve", action="store_true",
+                   help="skip the served-stream summary of the default line")
     p.add_argument("--copy-calibration", action="store_true",
                    help="also run a plain 1 GiB device copy (known traffic) for counter scaling")
     p.add_argument("--cpu-seconds", type=float, default=10.0,
@@ -202,6 +210,143 @@ def run_precision(args):
     print(json.dumps(out), flush=True)
 
 
+def _pct(xs, q):
+    import numpy as np
+
+    return float(np.percentile(np.asarray(xs, dtype=np.float64), q))
+
+
+def _serve_once(sk, sv, srv_args, reqs, Ys, idx, arrivals=None, pool=None):
+    """Run requests idx through a fresh server: all at once (arrivals None) or open
+    loop at the given arrival times (s, relative).  A is synthetic (filled by the
+    server at admission) unless a device pool is given (views pool[:m, :n])."""
+    with sk.SketchServer(*srv_args) as srv:
+        t0 = srv.now_us() + 2000.0
+        tickets, sched = [], []
+        for j, i in enumerate(idx):
+            r = reqs[i]
+            if arrivals is not None:
+                target = t0 + arrivals[j] * 1e6
+                while srv.now_us() < target:
+                    pass
+            else:
+                target = srv.now_us()
+            if pool is None:
+                req = sv.make_request(source=sv.SK_SRC_SYNTH, m=r["m"], n=r["n"],
+                                      a_seed=r["seed_a"], k=r["k"], seed=r["seed_omega"], Y=Ys[i])
+                tickets.append(srv.submit(req, Ys[i]))
+            else:
+                Av = pool[:r["m"], :r["n"]]
+                req = sv.make_request(A=Av, k=r["k"], seed=r["seed_omega"], Y=Ys[i])
+                tickets.append(srv.submit(req, Av, Ys[i]))
+            sched.append(target)
+        infos = [srv.wait(t, 600.0) for t in tickets]
+        st = srv.stats()
+    bad = [x for x in infos if x["state"] != sv.SK_REQ_DONE]
+    if bad:
+        raise RuntimeError(f"{len(bad)} served requests did not complete: {bad[:2]}")
+    nbytes = sum(4 * reqs[i]["m"] * reqs[i]["n"] for i in idx)
+    t_first = min(sched)
+    span_s = (max(x["t_done_us"] for x in infos) - t_first) * 1e-6
+    lat = [(x["t_done_us"] - a) * 1e-3 for x, a in zip(infos, sched)]
+    queue = [(x["t_admit_us"] - x["t_submit_us"]) * 1e-3 for x in infos]
+    lag = [(x["t_submit_us"] - a) * 1e-3 for x, a in zip(infos, sched)]
+    per_batch = {x["batch"]: (x["stage_us"], x["sketch_us"]) for x in infos}
+    return {"stage_us": sum(v[0] for v in per_batch.values()) / len(per_batch),
+            "sketch_us": sum(v[1] for v in per_batch.values()) / len(per_batch),
+            "busy_s": sum(v[0] + v[1] for v in per_batch.values()) * 1e-6,"requests": len(idx), "span_s": span_s, "req_per_s": len(idx) / span_s,
+            "GBps": nbytes / span_s / 1e9, "lat_ms": lat, "queue_ms": queue, "lag_ms": lag,
+            "batches": st["batches"], "max_running": st["max_running"],
+            "peak_bytes": st["peak_bytes_in_use"]}
+
+
+def run_serve(args, torch, quiet=False):
+    """Served form: a Poisson stream of uneven sketch requests (m, n log-uniform in
+    [1024, 32768], k uniform over {5, 16, 64}, distinct seeds) through the request
+    server.  Capacity = requests/s with the whole sample submitted at once; then open
+    loops at rho = 0.5, 0.8, 0.95 of it give latency percentiles (from the scheduled
+    arrival to completion).  A is synthetic, materialised by the server at admission
+    (counted in the memory footprint).  For comparison on the same GPU: the same
+    requests on a resident A (views of one 32768 x 32768 matrix), served and as
+    back-to-back direct sketch_gen_matmul calls."""
+    import paper_2603_20966_amd as sk
+    from paper_2603_20966_amd import serve as sv
+    from sketch_inputs import normal_matrix_device, request_stream
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n_req = args.serve_requests
+    base = request_stream(n_req, seed=2026, rate_per_s=1.0)
+    Ys = [torch.empty((r["m"], r["k"]), device=dev) for r in base]
+    torch.cuda.synchronize()
+    srv_args = (int(args.serve_budget_gib * (1 << 30)), args.serve_slots, 16, 4)
+    idx = list(range(n_req))
+    _serve_once(sk, sv, srv_args, base, Ys, idx[:min(64, n_req)])          # warm-up
+    cap = _serve_once(sk, sv, srv_args, base, Ys, idx)
+    runs = {}
+    for rho in (0.5, 0.8, 0.95):
+        stream = request_stream(n_req, seed=2026, rate_per_s=rho * cap["req_per_s"])
+        t_first = stream[0]["arrival_s"]
+        arr = [r["arrival_s"] - t_first for r in stream]
+        runs[rho] = _serve_once(sk, sv, srv_args, stream, Ys, idx, arrivals=arr)
+    # resident A: served vs direct calls on the same views
+    pool = normal_matrix_device(32768, 32768, seed=0, device=dev)
+    torch.cuda.synchronize()
+    res = _serve_once(sk, sv, srv_args, base, Ys, idx, pool=pool)
+    stream_ = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for r in base[:16]:
+        sk.sketch_gen_matmul(pool[:r["m"], :r["n"]], r["seed_omega"], r["k"], stream=stream_)
+    torch.cuda.synchronize()
+    e0.record(stream_)
+    for i, r in enumerate(base):
+        sk.sketch_gen_matmul(pool[:r["m"], :r["n"]], r["seed_omega"], r["k"], Y=Ys[i],
+                             stream=stream_)
+    e1.record(stream_)
+    torch.cuda.synchronize()
+    direct_s = e0.elapsed_time(e1) * 1e-3
+    nbytes = sum(4 * r["m"] * r["n"] for r in base)
+    del pool
+    torch.cuda.empty_cache()
+
+    def summary(x):
+        return {"req_per_s": round(x["req_per_s"], 1), "GBps": round(x["GBps"], 1),
+                "p50_ms": round(_pct(x["lat_ms"], 50), 3), "p99_ms": round(_pct(x["lat_ms"], 99), 3),
+                "mean_ms": round(sum(x["lat_ms"]) / len(x["lat_ms"]), 3),
+                "queue_p50_ms": round(_pct(x["queue_ms"], 50), 3),
+                "queue_p99_ms": round(_pct(x["queue_ms"], 99), 3),
+                "driver_lag_p99_ms": round(_pct(x["lag_ms"], 99), 3),
+                "batches": x["batches"], "mean_batch": round(x["requests"] / x["batches"], 2),
+                "max_running": x["max_running"], "peak_arena_GiB": round(x["peak_bytes"] / 2**30, 2),
+                "batch_stage_us": round(x["stage_us"], 1), "batch_sketch_us": round(x["sketch_us"], 1),
+                "device_busy_over_span": round(x["busy_s"] / x["span_s"], 3)}
+
+    head = runs[0.8]
+    out = {
+        "metric": "served sketch requests: p50/p99 latency at rho=0.8 of capacity",
+        "value": round(_pct(head["lat_ms"], 99), 3), "unit": "ms (p99)",
+        "p50_ms": round(_pct(head["lat_ms"], 50), 3), "p99_ms": round(_pct(head["lat_ms"], 99), 3),
+        "throughput_GBps": round(head["GBps"], 1),
+        "n_gpus": 1, "higher_is_better": False, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"Poisson stream of {n_req} requests (seed 2026), m, n log-uniform "
+                               "in [1024, 32768], k uniform over {5, 16, 64}, A fp32 N(0,1) "
+                               "filled by the server at admission (seed 1e6+r), Omega seed 2e6+r",
+                   "budget_GiB": args.serve_budget_gib, "slots": args.serve_slots,
+                   "max_batch": 16, "streams": 4},
+        "capacity": summary(cap),
+        "rho": {str(r): summary(x) for r, x in runs.items()},
+        "resident_A": {"served_GBps": round(res["GBps"], 1),
+                       "served_req_per_s": round(res["req_per_s"], 1),
+                       "direct_GBps": round(nbytes / direct_s / 1e9, 1),
+                       "direct_req_per_s": round(n_req / direct_s, 1),
+                       "note": "same requests on views of one resident 32768x32768 A: the "
+                               "server vs back-to-back sketch_gen_matmul calls on one stream"},
+    }
+    if not quiet:
+        print(json.dumps(out), flush=True)
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -214,6 +359,8 @@ def main():
         return run_ksweep(args)
     if args.workload == "precision":
         return run_precision(args)
+    if args.workload == "serve":
+        return run_serve(args, torch)
 
     import paper_2603_20966_amd as sk
     from sketch_inputs import normal_matrix_device
@@ -340,6 +487,14 @@ def main():
         out["copy_calibration_bytes"] = {"read": src.numel() * 4, "write": dst.numel() * 4}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, P, k, seed, args.cpu_seconds)
+    if not args.no_serve:
+        del A, shares, blocks
+        torch.cuda.empty_cache()
+        sv = run_serve(args, torch, quiet=True)
+        out["served"] = {"p50_ms": sv["p50_ms"], "p99_ms": sv["p99_ms"],
+                         "throughput_GBps": sv["throughput_GBps"], "at": "rho=0.8 of capacity",
+                         "capacity": sv["capacity"], "resident_A": sv["resident_A"],
+                         "workload": sv["config"]["workload"]}
     print(json.dumps(out), flush=True)
 
 

@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define SKETCH_ABI_VERSION 1
+#define SKETCH_ABI_VERSION 2
 
 enum sk_status {
     SK_OK = 0,
@@ -63,7 +63,8 @@ enum sk_status {
     SK_ENOMEM = -6,        /* (serving) device memory exhausted                   */
     SK_EUNSUPPORTED = -7,  /* valid request this build does not handle            */
     SK_EBUDGET = -8,       /* (serving) request larger than the memory budget     */
-    SK_EQUEUE = -9         /* (serving) queue full or unknown ticket              */
+    SK_EQUEUE = -9,        /* (serving) queue full or unknown ticket              */
+    SK_ETIMEOUT = -10      /* (serving) wait ended before the request finished    */
 };
 
 /* Storage type of A. */

@@ -1,7 +1,8 @@
 """MI355X (gfx950) library for the sketch Y = A * Omega(seed) with a generated operand.
 
 Python binding of the C ABI in ``include/sketch.h`` (libsketch.so, built by
-``paper_2603_20966_amd.build``).  The functions carry the ABI's names and only
+``paper_2603_20966_amd.build``); the request server of ``include/sketch_serve.h``
+is bound in ``paper_2603_20966_amd.serve``.  The functions carry the ABI's names and only
 marshal arguments: torch tensors give device pointers and the current HIP
 stream; every step of the computation runs in the library's kernels.  There is
 no fallback: if the library is not built, every call raises.
@@ -26,7 +27,7 @@ SK_A_F32, SK_A_BF16, SK_A_FP8_E4M3 = 0, 1, 2
 SK_Y_F32, SK_Y_F64 = 0, 1
 STATUS = {0: "SK_OK", -1: "SK_EINVAL", -2: "SK_EDTYPE", -3: "SK_EALIGN", -4: "SK_EWORKSPACE",
           -5: "SK_EHIP", -6: "SK_ENOMEM", -7: "SK_EUNSUPPORTED", -8: "SK_EBUDGET",
-          -9: "SK_EQUEUE"}
+          -9: "SK_EQUEUE", -10: "SK_ETIMEOUT"}
 
 _lib = None
 _lock = threading.Lock()
@@ -299,8 +300,10 @@ def sketch_quantize(A: torch.Tensor, dst: str, *, stream=None):
     raise ValueError("dst must be 'bf16' or 'fp8'")
 
 
+from .serve import SketchServer, make_request, sk_request_footprint  # noqa: E402
+
 __all__ = ["sketch_abi_version", "sketch_status_string", "sketch_workspace_size",
-           "sketch_strip_width",
+           "sketch_strip_width", "SketchServer", "make_request", "sk_request_footprint",
            "sketch_gen_matmul", "sketch_gen_matmul_reduce",
            "sketch_gen_omega", "sketch_matmul_omega", "sketch_philox_raw", "sketch_quantize",
            "sketch_trace_events", "SketchError", "lib", "LIB_PATH"]

@@ -6,19 +6,12 @@
 #include <string.h>
 
 #include "../../include/sketch.h"
+#include "sk_check.hpp"
 #include "sk_internal.hpp"
 
 namespace {
 
-constexpr int64_t kMaxRow = (int64_t)1 << 62;
-constexpr int64_t kMaxCol = (int64_t)1 << 32;
-constexpr int64_t kMaxK = 256;
-constexpr int64_t kMaxGridY = 65535;
-
-int elem_size(int a_dtype) { return a_dtype == SK_A_F32 ? 4 : a_dtype == SK_A_BF16 ? 2 : 1; }
-bool adtype_ok(int t) { return t == SK_A_F32 || t == SK_A_BF16 || t == SK_A_FP8_E4M3; }
-bool ydtype_ok(int t) { return t == SK_Y_F32 || t == SK_Y_F64; }
-bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+using namespace sk::check;
 
 int from_hip(hipError_t e) { return e == hipSuccess ? SK_OK : SK_EHIP; }
 
@@ -29,33 +22,6 @@ sk::TraceEvents take_trace() {
     sk::TraceEvents t = g_trace;
     g_trace = sk::TraceEvents{};
     return t;
-}
-
-// Checks shared by every product call; fills the Y part of the launch.
-int check_common(int a_dtype, int64_t m, int64_t k, int64_t col0, const void* Y, int y_dtype,
-                 int64_t ldy, int beta) {
-    if (!adtype_ok(a_dtype) || !ydtype_ok(y_dtype)) return SK_EDTYPE;
-    if (m < 0 || k < 0 || k > kMaxK) return SK_EINVAL;
-    if (beta != 0 && beta != 1) return SK_EINVAL;
-    if (col0 < 0 || col0 + k > kMaxCol) return SK_EINVAL;
-    if (m == 0 || k == 0) return SK_OK;
-    if (Y == nullptr || ldy < k) return SK_EINVAL;
-    if (((uintptr_t)Y & (y_dtype == SK_Y_F64 ? 7u : 3u)) != 0) return SK_EALIGN;
-    // grid: rows per workgroup are at most 1024 (streaming kernel) or exactly
-    // 256 (matrix-core kernel), row blocks at most 65535
-    if (m > kMaxGridY * (sk::use_mfma(a_dtype, k) ? 256 : 1024)) return SK_EUNSUPPORTED;
-    return SK_OK;
-}
-
-int check_block(const void* A, int a_dtype, int64_t m, int64_t n, int64_t lda, int64_t row0,
-                const float* scales) {
-    if (n < 0 || row0 < 0 || row0 > kMaxRow - n) return SK_EINVAL;
-    if (n == 0 || m == 0) return SK_OK;
-    if (A == nullptr || lda < n) return SK_EINVAL;
-    if (!aligned16(A) || (lda * elem_size(a_dtype)) % 16 != 0) return SK_EALIGN;
-    if (a_dtype == SK_A_FP8_E4M3 && scales == nullptr) return SK_EINVAL;
-    if (scales && ((uintptr_t)scales & 3u)) return SK_EALIGN;
-    return SK_OK;
 }
 
 size_t workspace_for(int op, int adtype, int64_t m, int64_t n, int64_t k, int64_t P) {
@@ -104,6 +70,7 @@ const char* sketch_status_string(int status) {
     case SK_EUNSUPPORTED: return "unsupported request";
     case SK_EBUDGET: return "request exceeds the memory budget";
     case SK_EQUEUE: return "queue full or unknown ticket";
+    case SK_ETIMEOUT: return "wait timed out before the request finished";
     default: return "unknown status";
     }
 }

@@ -574,6 +574,8 @@ hipError_t dispatch_k(int kc, const KArgs& a, dim3 grid, hipStream_t s, const Tr
     }
 }
 
+}  // namespace
+
 // Compute units of the current device (cached per device).
 int device_cus() {
     static int cus[64] = {0};
@@ -605,8 +607,6 @@ int64_t rows_per_tile(int64_t m, int64_t strips, int64_t ncg) {
     if (forced == 0) R = std::min<int64_t>(R, 512);
     return std::max<int64_t>(kRowQuantum, R);
 }
-
-}  // namespace
 
 int64_t count_strips(const GemmLaunch& g) {
     const int64_t C = strip_width_for(g.adtype, g.k);
@@ -664,29 +664,69 @@ hipError_t launch_gemm_stream(const GemmLaunch& g) {
     }
 }
 
-hipError_t launch_gemm_batch(const BatchArgs& a, int kclass, int adtype, int grid,
-                             hipStream_t s) {
-    if (a.count == 0 || a.total_tiles == 0) return hipSuccess;
-    grid = std::max(8, (grid + 7) / 8 * 8);   // the tile walk assumes a multiple of 8
-    const dim3 g((unsigned)grid), blk(kWgThreads);
-#define SK_BATCH(KK)                                                                       \
-    case KK:                                                                               \
-        if (adtype == 0) hipLaunchKernelGGL((k_gemm_batch<KK, 0>), g, blk, 0, s, a);       \
-        else if (adtype == 1) hipLaunchKernelGGL((k_gemm_batch<KK, 1>), g, blk, 0, s, a);  \
-        else hipLaunchKernelGGL((k_gemm_batch<KK, 2>), g, blk, 0, s, a);                   \
-        break;
-    switch (kclass) {
-        SK_BATCH(1) SK_BATCH(2) SK_BATCH(3) SK_BATCH(4) SK_BATCH(5) SK_BATCH(6) SK_BATCH(8)
-        SK_BATCH(12) SK_BATCH(16)
-    default: return hipErrorInvalidValue;
-    }
-#undef SK_BATCH
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+hipError_t launch_reduce_batch(const BatchArgs& a, hipStream_t s) {
     if (a.total_outputs > 0)
         hipLaunchKernelGGL(k_reduce_batch, dim3((unsigned)((a.total_outputs + 255) / 256)),
                            dim3(256), 0, s, a);
     return hipGetLastError();
+}
+
+namespace {
+
+// Persistent grid of a batch: the workgroups one resident round holds
+// (occupancy x compute units), at most one per tile, a multiple of 8 so that
+// every workgroup stays on one XCD's tile range.
+int resident_grid(int per_cu, int64_t total_tiles, int grid) {
+    if (grid <= 0) grid = std::max(1, per_cu) * device_cus();
+    const int64_t cap = (total_tiles + 7) / 8 * 8;
+    grid = (int)std::min<int64_t>(grid, cap);
+    return std::max(8, (grid + 7) / 8 * 8);
+}
+
+template <int K, int ADT>
+hipError_t run_batch(const BatchArgs& a, int grid, hipStream_t s) {
+    static const int per_cu = [] {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gemm_batch<K, ADT>, kWgThreads, 0) !=
+            hipSuccess)
+            n = 1;
+        return n;
+    }();
+    grid = resident_grid(per_cu, a.total_tiles, grid);
+    hipLaunchKernelGGL((k_gemm_batch<K, ADT>), dim3((unsigned)grid), dim3(kWgThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int ADT>
+hipError_t run_batch_k(int kclass, const BatchArgs& a, int grid, hipStream_t s) {
+    switch (kclass) {
+    case 1: return run_batch<1, ADT>(a, grid, s);
+    case 2: return run_batch<2, ADT>(a, grid, s);
+    case 3: return run_batch<3, ADT>(a, grid, s);
+    case 4: return run_batch<4, ADT>(a, grid, s);
+    case 5: return run_batch<5, ADT>(a, grid, s);
+    case 6: return run_batch<6, ADT>(a, grid, s);
+    case 8: return run_batch<8, ADT>(a, grid, s);
+    case 12: return run_batch<12, ADT>(a, grid, s);
+    case 16: return run_batch<16, ADT>(a, grid, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+int batch_grid(int per_cu, int64_t total_tiles, int grid) {
+    return resident_grid(per_cu, total_tiles, grid);
+}
+
+hipError_t launch_gemm_batch(const BatchArgs& a, int kclass, int adtype, int grid,
+                             hipStream_t s) {
+    if (a.count == 0 || a.total_tiles == 0) return hipSuccess;
+    hipError_t e = adtype == 0   ? run_batch_k<0>(kclass, a, grid, s)
+                   : adtype == 1 ? run_batch_k<1>(kclass, a, grid, s)
+                                 : run_batch_k<2>(kclass, a, grid, s);
+    if (e != hipSuccess) return e;
+    return launch_reduce_batch(a, s);
 }
 
 }  // namespace sk

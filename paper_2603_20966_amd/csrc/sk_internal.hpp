@@ -29,11 +29,13 @@ constexpr int strip_width(int kclass, int adtype) {
                        : (kclass <= 4 ? 4096 : kclass <= 8 ? 2048 : 1024);
 }
 
-// The matrix-core kernel takes FP32 A once k > 8: past that the VALU path
-// spends more than half its issue slots on FMAs at HBM speed (measured at
-// k = 16: 4.1 TB/s on VALU).  Its strips are 2048 columns.
+// The matrix-core kernel takes FP32 A once k exceeds one column group (16).
+// At k = 16 the VALU path is still faster (measured on 65536 x 16384:
+// 4.1 TB/s on VALU, 2.9 TB/s with one 16-column matrix-core tile).  Its strips
+// are 2048 columns.
 constexpr int kMfmaStrip = 2048;
-constexpr int kMfmaMinK = 9;
+constexpr int kMfmaRows = 256;     // rows of a matrix-core tile
+constexpr int kMfmaMinK = kColGroup + 1;
 constexpr bool use_mfma(int adtype, int64_t k) { return adtype == 0 && k >= kMfmaMinK; }
 
 // Strip width used for a sketch of width k with A stored as adtype.
@@ -104,9 +106,29 @@ int64_t count_strips(const GemmLaunch& g);
 size_t gemm_workspace_bytes(int64_t m, int64_t strips, int64_t k);
 
 hipError_t launch_gemm_stream(const GemmLaunch& g);
-// Streaming-kernel batch: all requests share the tile class (kclass, adtype).
+// Streaming-kernel batch: all requests share the tile class (kclass, adtype);
+// followed by the batched FP64 strip sums.  grid <= 0: one resident round of
+// workgroups (occupancy x compute units), at most one per tile.
 hipError_t launch_gemm_batch(const BatchArgs& a, int kclass, int adtype, int grid, hipStream_t s);
+hipError_t launch_reduce_batch(const BatchArgs& a, hipStream_t s);
 hipError_t launch_gemm_mfma(const GemmLaunch& g);
+// Matrix-core batch (FP32 A, generated Omega): every request has the same N-tile
+// count nt; BatchReq.rowblocks counts kMfmaRows-row tiles, strips kMfmaStrip columns.
+hipError_t launch_gemm_mfma_batch(const BatchArgs& a, int nt, int grid, hipStream_t s);
+int mfma_ntiles(int64_t k);
+// Persistent grid for total_tiles tiles of a kernel holding per_cu workgroups
+// per compute unit (grid > 0: that size, capped at the tile count); a
+// multiple of 8.
+int batch_grid(int per_cu, int64_t total_tiles, int grid);
+// Compute units of the current device; rows per streaming tile for m rows,
+// `strips` strips and ncg column groups.
+int device_cus();
+int64_t rows_per_tile(int64_t m, int64_t strips, int64_t ncg);
+// A[i][j] ~ N(0,1) for a synthetic request: Philox4x32-10 on counters
+// (j/4, i, 0, 1) (the last word keeps the stream apart from Omega's, whose
+// last word is 0), Box-Muller with the hardware transcendentals.
+hipError_t launch_fill_normal(float* A, int64_t m, int64_t n, int64_t lda, uint64_t seed,
+                              hipStream_t s);
 hipError_t launch_reduce_partials(const float* partials, int S, int64_t m, int64_t k, void* Y,
                                   int y_f64, int64_t ldy, int beta, hipStream_t s);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);

@@ -1,4 +1,4 @@
-// Matrix-core kernel for Y = A * Omega(seed) with a wide sketch (k > 8) on gfx950.
+// Matrix-core kernel for Y = A * Omega(seed) with a wide sketch (k > 16) on gfx950.
 //
 // Once k is large the product is a dense contraction (2k flops per A element;
 // non-packed FP32 VALU FMAs reach their ridge near k = 20, and above k ~ 8
@@ -25,6 +25,8 @@
 // Strip partials are FP32 in [S][m][k]; the FP64 strip sum is the shared
 // reduction kernel.  The order of every sum depends only on the strip
 // boundaries, so results are layout independent and reproducible.
+#include <algorithm>
+
 #include "sk_device.hpp"
 #include "sk_internal.hpp"
 
@@ -38,6 +40,7 @@ typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 
 constexpr int kTM = 4;        // M-tiles (16 rows) per wave
 constexpr int kBM = 4 * kTM * 16;   // rows per workgroup
+static_assert(kBM == kMfmaRows, "tile rows");
 constexpr int kKC = 16;       // contraction columns per chunk
 constexpr int kLdsRow = 20;   // floats per LDS column (16 + 4 pad)
 
@@ -64,42 +67,49 @@ __device__ __forceinline__ void lds_barrier_m() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-template <int NT, bool GEN>
-__global__ __launch_bounds__(256) void k_gemm_mfma(const MArgs args) {
-    constexpr int BN = 16 * NT;
-    __shared__ float om[2][BN][kLdsRow];
+// One tile: rows [row_base, row_base + 256) of a block, one strip of its
+// columns, sketch columns [n_base, n_base + 16*NT).
+struct MTile {
+    const unsigned char* A;   // the block's A
+    int64_t lda, n, row0;     // the block's ld, width, first Omega row
+    const float* scales;
+    int64_t m, k;
+    int64_t col_begin;        // first column of the strip inside the block
+    int64_t block_row;        // first row of the workgroup (before the wave offset)
+    int n_base;
+    uint32_t key0, key1, col0;
+    const float* omega;
+    int64_t ldo;
+    void* Y;
+    int64_t ldy;
+    int y_f64, beta;
+    float* partials;
+    int64_t strip;            // strip index in the partial array
+    bool single;
+};
 
+template <int NT, bool GEN>
+__device__ __forceinline__ void mfma_tile(const MTile& t, float (*om)[16 * NT][kLdsRow]) {
+    constexpr int BN = 16 * NT;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int g = lane >> 4;      // contraction group of the lane (A and B operands)
     const int i16 = lane & 15;    // row (A operand) / column (B operand) within a tile
 
-    // ---- strip, row block, column block --------------------------------------
-    const int strip = blockIdx.x;
-    int b = 0;
-    int64_t sib = strip;
-    for (; b < args.P; ++b) {
-        const int64_t sb = (args.blk[b].n + kMfmaStrip - 1) / kMfmaStrip;
-        if (sib < sb) break;
-        sib -= sb;
-    }
-    const BlockDesc blk = args.blk[b];
-    const int64_t col_begin = sib * kMfmaStrip;
-    const int w = (int)min<int64_t>(kMfmaStrip, blk.n - col_begin);
+    const int w = (int)min<int64_t>(kMfmaStrip, t.n - t.col_begin);
     const int nchunks = (w + kKC - 1) / kKC;
-    const int64_t row_base = (int64_t)blockIdx.y * kBM + wave * (kTM * 16);
-    const int n_base = blockIdx.z * BN;                 // first sketch column of the block
-    const int kb = (int)min<int64_t>(BN, args.k - n_base);
+    const int64_t row_base = t.block_row + wave * (kTM * 16);
+    const int n_base = t.n_base;
+    const int kb = (int)min<int64_t>(BN, t.k - n_base);
 
     // ---- A operand loads ----------------------------------------------------------
-    const unsigned char* Ab = static_cast<const unsigned char*>(blk.A);
-    const int64_t lda4 = blk.lda * 4;
+    const int64_t lda4 = t.lda * 4;
     const unsigned char* arow[kTM];
 #pragma unroll
     for (int tm = 0; tm < kTM; ++tm) {
-        const int64_t r = min<int64_t>(row_base + tm * 16 + i16, args.m - 1);
-        arow[tm] = Ab + r * lda4 + (col_begin + 4 * g) * 4;
+        const int64_t r = min<int64_t>(row_base + tm * 16 + i16, t.m - 1);
+        arow[tm] = t.A + r * lda4 + (t.col_begin + 4 * g) * 4;
     }
     auto load_a = [&](v4f* a, int c) {
         if (c >= nchunks) return;
@@ -129,24 +139,24 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(const MArgs args) {
         const int buf = c & 1;
         const int kvalid = min(kKC, w - c * kKC);
         if constexpr (GEN) {
-            const int64_t g0 = blk.row0 + col_begin + (int64_t)c * kKC;  // global Omega row of local 0
+            const int64_t g0 = t.row0 + t.col_begin + (int64_t)c * kKC;  // global Omega row of local 0
             const int64_t q_lo = g0 >> 2;
             const int nq = (int)(((g0 + kKC - 1) >> 2) - q_lo + 1);       // 4, or 5 if unaligned
             const int items = nq * kb;
             for (int it = tid; it < items; it += 256) {
                 const int qi = it / kb;
                 const int n = it - qi * kb;
-                const float4 z = omega4((uint64_t)(q_lo + qi), args.col0 + (uint32_t)(n_base + n),
-                                        args.key0, args.key1);
+                const float4 z = omega4((uint64_t)(q_lo + qi), t.col0 + (uint32_t)(n_base + n),
+                                        t.key0, t.key1);
                 const int kl0 = (int)(4 * (q_lo + qi) - g0);
                 if (kl0 >= 0 && (kl0 & 3) == 0 && kl0 + 3 < kvalid) {
                     *reinterpret_cast<float4*>(&om[buf][n][kl0]) = z;
                 } else {
                     const float zz[4] = {z.x, z.y, z.z, z.w};
 #pragma unroll
-                    for (int t = 0; t < 4; ++t) {
-                        const int kl = kl0 + t;
-                        if (kl >= 0 && kl < kKC) om[buf][n][kl] = (kl < kvalid) ? zz[t] : 0.0f;
+                    for (int u = 0; u < 4; ++u) {
+                        const int kl = kl0 + u;
+                        if (kl >= 0 && kl < kKC) om[buf][n][kl] = (kl < kvalid) ? zz[u] : 0.0f;
                     }
                 }
             }
@@ -155,7 +165,7 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(const MArgs args) {
                 const int kl = it / kb;
                 const int n = it - kl * kb;
                 om[buf][n][kl] = (kl < kvalid)
-                                     ? args.omega[(col_begin + (int64_t)c * kKC + kl) * args.ldo + n_base + n]
+                                     ? t.omega[(t.col_begin + (int64_t)c * kKC + kl) * t.ldo + n_base + n]
                                      : 0.0f;
             }
         }
@@ -203,8 +213,6 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(const MArgs args) {
     }
 
     // ---- write: lane (g, j) holds rows 4g..4g+3, column j of each tile ----------------
-    const bool single = (args.S_total == 1);
-    const float* scales = blk.scales;
 #pragma unroll
     for (int tm = 0; tm < kTM; ++tm) {
 #pragma unroll
@@ -215,25 +223,111 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(const MArgs args) {
 #pragma unroll
             for (int rr = 0; rr < 4; ++rr) {
                 const int64_t r = row_base + tm * 16 + 4 * g + rr;
-                if (r >= args.m) continue;
+                if (r >= t.m) continue;
                 float v = acc[tm][nt][rr];
-                if (scales) v *= scales[r >> 7];
-                if (single) {
+                if (t.scales) v *= t.scales[r >> 7];
+                if (t.single) {
                     double y = (double)v;
-                    if (args.y_f64) {
-                        double* Yp = static_cast<double*>(args.Y) + r * args.ldy + col;
-                        if (args.beta) y += *Yp;
+                    if (t.y_f64) {
+                        double* Yp = static_cast<double*>(t.Y) + r * t.ldy + col;
+                        if (t.beta) y += *Yp;
                         *Yp = y;
                     } else {
-                        float* Yp = static_cast<float*>(args.Y) + r * args.ldy + col;
-                        if (args.beta) y += (double)*Yp;
+                        float* Yp = static_cast<float*>(t.Y) + r * t.ldy + col;
+                        if (t.beta) y += (double)*Yp;
                         *Yp = (float)y;
                     }
                 } else {
-                    args.partials[((int64_t)strip * args.m + r) * args.k + col] = v;
+                    t.partials[(t.strip * t.m + r) * t.k + col] = v;
                 }
             }
         }
+    }
+}
+
+// One call: grid (strips of all blocks, 256-row tiles, sketch-column blocks).
+template <int NT, bool GEN>
+__global__ __launch_bounds__(256) void k_gemm_mfma(const MArgs args) {
+    __shared__ float om[2][16 * NT][kLdsRow];
+    const int strip = blockIdx.x;
+    int b = 0;
+    int64_t sib = strip;
+    for (; b < args.P; ++b) {
+        const int64_t sb = (args.blk[b].n + kMfmaStrip - 1) / kMfmaStrip;
+        if (sib < sb) break;
+        sib -= sb;
+    }
+    const BlockDesc& blk = args.blk[b];
+    MTile t;
+    t.A = static_cast<const unsigned char*>(blk.A);
+    t.lda = blk.lda;
+    t.n = blk.n;
+    t.row0 = blk.row0;
+    t.scales = blk.scales;
+    t.m = args.m;
+    t.k = args.k;
+    t.col_begin = sib * kMfmaStrip;
+    t.block_row = (int64_t)blockIdx.y * kBM;
+    t.n_base = blockIdx.z * 16 * NT;
+    t.key0 = args.key0;
+    t.key1 = args.key1;
+    t.col0 = args.col0;
+    t.omega = args.omega;
+    t.ldo = args.ldo;
+    t.Y = args.Y;
+    t.ldy = args.ldy;
+    t.y_f64 = args.y_f64;
+    t.beta = args.beta;
+    t.partials = args.partials;
+    t.strip = strip;
+    t.single = (args.S_total == 1);
+    mfma_tile<NT, GEN>(t, om);
+}
+
+// A batch of independent requests (serving): the tiles of each request are the
+// ones a call for that request alone would run, walked by a fixed grid in an
+// XCD-grouped order, so each result does not depend on the batch.
+template <int NT>
+__global__ __launch_bounds__(256) void k_gemm_mfma_batch(const BatchArgs args) {
+    __shared__ float om[2][16 * NT][kLdsRow];
+    const int64_t T8 = (args.total_tiles + 7) / 8;
+    bool first = true;
+    for (int64_t v = blockIdx.x; v < 8 * T8; v += gridDim.x) {   // gridDim.x is a multiple of 8
+        const int64_t tt = (v % 8) * T8 + v / 8;
+        if (tt >= args.total_tiles) continue;
+        int q = 0;
+        while (q + 1 < args.count && tt >= args.req[q + 1].tile_begin) ++q;
+        const BatchReq& rq = args.req[q];
+        const int64_t lt = tt - rq.tile_begin;
+        const int64_t strip = lt % rq.strips;
+        const int64_t rb = (lt / rq.strips) % rq.rowblocks;
+        const int nb = (int)(lt / ((int64_t)rq.strips * rq.rowblocks));
+        MTile t;
+        t.A = static_cast<const unsigned char*>(rq.A);
+        t.lda = rq.lda;
+        t.n = rq.n;
+        t.row0 = rq.row0;
+        t.scales = rq.scales;
+        t.m = rq.m;
+        t.k = rq.k;
+        t.col_begin = strip * kMfmaStrip;
+        t.block_row = rb * kBM;
+        t.n_base = nb * 16 * NT;
+        t.key0 = (uint32_t)rq.seed;
+        t.key1 = (uint32_t)(rq.seed >> 32);
+        t.col0 = rq.col0;
+        t.omega = nullptr;
+        t.ldo = 0;
+        t.Y = rq.Y;
+        t.ldy = rq.ldy;
+        t.y_f64 = rq.y_f64;
+        t.beta = rq.beta;
+        t.partials = rq.partials;
+        t.strip = strip;
+        t.single = (rq.strips == 1);
+        if (!first) lds_barrier_m();   // every wave is done with the previous tile's LDS
+        first = false;
+        mfma_tile<NT, true>(t, om);
     }
 }
 
@@ -246,7 +340,6 @@ hipError_t launch_m(const MArgs& a, dim3 grid, hipStream_t s) {
 template <bool GEN>
 hipError_t dispatch_m(int nt, const MArgs& a, dim3 grid, hipStream_t s) {
     switch (nt) {
-    case 1: return launch_m<1, GEN>(a, grid, s);
     case 2: return launch_m<2, GEN>(a, grid, s);
     case 4: return launch_m<4, GEN>(a, grid, s);
     default: return launch_m<8, GEN>(a, grid, s);
@@ -256,7 +349,7 @@ hipError_t dispatch_m(int nt, const MArgs& a, dim3 grid, hipStream_t s) {
 }  // namespace
 
 // N-tiles (of 16 sketch columns) per workgroup for a sketch of width k.
-int mfma_ntiles(int64_t k) { return k <= 16 ? 1 : k <= 32 ? 2 : k <= 64 ? 4 : 8; }
+int mfma_ntiles(int64_t k) { return k <= 32 ? 2 : k <= 64 ? 4 : 8; }
 
 hipError_t launch_gemm_mfma(const GemmLaunch& g) {
     const int nt = mfma_ntiles(g.k);
@@ -291,6 +384,37 @@ hipError_t launch_gemm_mfma(const GemmLaunch& g) {
                                           g.beta, g.stream);
     if (tr.end) (void)hipEventRecord(tr.end, g.stream);
     return e;
+}
+
+namespace {
+
+template <int NT>
+hipError_t run_mfma_batch(const BatchArgs& a, int grid, hipStream_t s) {
+    static const int per_cu = [] {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gemm_mfma_batch<NT>, 256, 0) !=
+            hipSuccess)
+            n = 1;
+        return n;
+    }();
+    grid = batch_grid(per_cu, a.total_tiles, grid);
+    hipLaunchKernelGGL((k_gemm_mfma_batch<NT>), dim3((unsigned)grid), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_gemm_mfma_batch(const BatchArgs& a, int nt, int grid, hipStream_t s) {
+    if (a.count == 0 || a.total_tiles == 0) return hipSuccess;
+    hipError_t e;
+    switch (nt) {
+    case 2: e = run_mfma_batch<2>(a, grid, s); break;
+    case 4: e = run_mfma_batch<4>(a, grid, s); break;
+    case 8: e = run_mfma_batch<8>(a, grid, s); break;
+    default: return hipErrorInvalidValue;
+    }
+    if (e != hipSuccess) return e;
+    return launch_reduce_batch(a, s);
 }
 
 }  // namespace sk

@@ -35,6 +35,42 @@ __global__ void k_gen_omega(uint32_t k0, uint32_t k1, int64_t row0, int64_t n, i
     }
 }
 
+// Synthetic N(0,1) matrix (load generation, not the sketch's operand): thread
+// (i, q) writes columns 4q .. 4q+3 of row i from one Philox4x32-10 call on the
+// counter (q, i, 0, 1) and two Box-Muller pairs evaluated with the hardware
+// transcendentals (v_log_f32 = log2, v_sin_f32 / v_cos_f32 in revolutions,
+// v_sqrt_f32): a few instructions per value, deterministic on the device.
+__device__ __forceinline__ void fast_pair(uint32_t re, uint32_t ro, float& zc, float& zs) {
+    const float ue = (float)(odd24(re)) * 0x1p-24f;   // (0, 1)
+    const float uo = (float)(odd24(ro)) * 0x1p-24f;
+    const float rho = __builtin_amdgcn_sqrtf(-2.0f * 0x1.62e430p-1f * __builtin_amdgcn_logf(ue));
+    zc = rho * __builtin_amdgcn_cosf(uo);
+    zs = rho * __builtin_amdgcn_sinf(uo);
+}
+
+__global__ void k_fill_normal(float* A, int64_t m, int64_t n, int64_t lda, uint32_t k0,
+                              uint32_t k1) {
+    const int64_t nq = (n + 3) >> 2;
+    for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < m * nq;
+         it += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = it / nq;
+        const int64_t q = it - i * nq;
+        Words4 ctr{(uint32_t)q, (uint32_t)i, 0u, 1u};
+        const Words4 r = philox4x32_10(ctr, k0, k1);
+        float z[4];
+        fast_pair(r.x, r.y, z[0], z[1]);
+        fast_pair(r.z, r.w, z[2], z[3]);
+        float* row = A + i * lda + 4 * q;
+        if (4 * q + 3 < n && (lda & 3) == 0 && ((uintptr_t)A & 15) == 0) {
+            *reinterpret_cast<float4*>(row) = make_float4(z[0], z[1], z[2], z[3]);
+        } else {
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                if (4 * q + t < n) row[t] = z[t];
+        }
+    }
+}
+
 __global__ void k_zero(uint32_t* p, int64_t words) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words;
          i += (int64_t)gridDim.x * blockDim.x)
@@ -175,6 +211,16 @@ hipError_t launch_gen_omega(uint64_t seed, int64_t row0, int64_t n, int64_t col0
     hipLaunchKernelGGL(k_gen_omega, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, s,
                        (uint32_t)seed, (uint32_t)(seed >> 32), row0, n, col0, k, Om, ldo, q_lo,
                        nq);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_normal(float* A, int64_t m, int64_t n, int64_t lda, uint64_t seed,
+                              hipStream_t s) {
+    if (m == 0 || n == 0) return hipSuccess;
+    const int64_t items = m * ((n + 3) >> 2);
+    const unsigned blocks = (unsigned)std::min<int64_t>((items + 255) / 256, 8 * 1024);
+    hipLaunchKernelGGL(k_fill_normal, dim3(blocks), dim3(256), 0, s, A, m, n, lda, (uint32_t)seed,
+                       (uint32_t)(seed >> 32));
     return hipGetLastError();
 }
 

@@ -12,7 +12,7 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "sketch.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("sketch.h", "sketch_serve.h")]
 
 import paper_2603_20966_amd as sk  # noqa: E402
 
@@ -25,26 +25,31 @@ PW = 0x30000
 
 
 def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(sketch_[a-z_0-9]+)\s*\(", text)))
+    names = set()
+    for h in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b((?:sketch|sk)_[a-z_0-9]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_header_symbols_exported():
     L = sk.lib()
     names = declared_functions()
-    assert len(names) >= 9
+    assert len(names) >= 18
+    assert {"sketch_gen_matmul", "sketch_gen_matmul_reduce", "sk_server_create",
+            "sk_server_submit", "sk_server_poll", "sk_server_cancel",
+            "sk_server_destroy"} <= set(names)
     for name in names:
         assert hasattr(L, name), name
     # and nothing exported under the ABI prefix that the header does not declare
     out = os.popen(f"nm -D --defined-only {sk.LIB_PATH}").read()
-    exported = set(re.findall(r" T (sketch_[a-z_0-9]+)$", out, flags=re.M))
+    exported = set(re.findall(r" T ((?:sketch|sk)_[a-z_0-9]+)$", out, flags=re.M))
     assert exported == set(names)
 
 
 def test_version_and_status_strings():
-    assert sk.sketch_abi_version() == 1
-    for st in range(-9, 1):
+    assert sk.sketch_abi_version() == 2
+    for st in range(-10, 1):
         assert sk.sketch_status_string(st) != "unknown status"
     assert sk.sketch_status_string(-100) == "unknown status"
 
@@ -139,9 +144,12 @@ def test_workspace_size_rules():
     assert b >= (32 + 8) * 32768 * 5 * 4                # bound valid for any 8-way split
     assert ws(2, F32, 1, 1, 1, 1) == 0 and ws(0, 5, 1, 1, 1, 1) == 0 and ws(1, F32, 1, 1, 1, 0) == 0
     assert ws(0, F32, 100, 5000, 300, 1) == 0           # k > 256 is invalid
-    # matrix-core path (FP32, k > 8): 2048-column strips
-    assert ws(0, F32, 4096, 32768, 16, 1) == 16 * 4096 * 16 * 4
-    assert sk.sketch_strip_width(F32, 5) == 1024 and sk.sketch_strip_width(F32, 9) == 2048
+    # a wider VALU sketch uses narrower strips; the matrix-core path (FP32, k > 16)
+    # uses 2048-column strips
+    assert ws(0, F32, 4096, 32768, 16, 1) == 64 * 4096 * 16 * 4
+    assert ws(0, F32, 4096, 32768, 17, 1) == 16 * 4096 * 17 * 4
+    assert sk.sketch_strip_width(F32, 5) == 1024 and sk.sketch_strip_width(F32, 9) == 512
+    assert sk.sketch_strip_width(F32, 17) == 2048
     assert sk.sketch_strip_width(BF16, 5) == 2048 and sk.sketch_strip_width(FP8, 4) == 4096
 
 
@@ -153,3 +161,51 @@ def test_python_binding_requires_library(monkeypatch, tmp_path):
     monkeypatch.setattr(mod, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="no CPU fallback"):
         mod.lib()
+
+
+def test_request_footprint_rule():
+    """Serving admission charges FP32 strip partials (S > 1 strips) plus any staged A,
+    each rounded up to 256 bytes; invalid requests have footprint 0.  Host-only."""
+    from paper_2603_20966_amd import serve as sv
+
+    def req(**kw):
+        r = sv.SkRequest()
+        r.a_source, r.a_dtype, r.A, r.m, r.n, r.lda = sv.SK_SRC_DEVICE, F32, PA, 512, 4096, 4096
+        r.seed, r.k, r.Y, r.y_dtype, r.ldy = 1, 5, PB, YF32, 5
+        for key, v in kw.items():
+            setattr(r, key, v)
+        return r
+
+    fp = sv.sk_request_footprint
+    assert fp(req()) == 4 * 512 * 5 * 4                       # 4 strips of 1024 columns
+    assert fp(req(n=1000, lda=1000)) == 0                     # one strip: no partials
+    assert fp(req(n=1000, lda=1000, m=3, k=1, ldy=1)) == 0
+    assert fp(req(k=64, ldy=64)) == 2 * 512 * 64 * 4          # matrix core: 2048-column strips
+    assert fp(req(a_source=sv.SK_SRC_SYNTH, A=None)) == 512 * 4096 * 4 + 4 * 512 * 5 * 4
+    # staged rows padded to 16 bytes, each part rounded to 256 bytes
+    assert fp(req(a_source=sv.SK_SRC_HOST, n=1001, lda=1001, m=3, k=1, ldy=1)) == 12288 + 0
+    assert fp(req(a_source=sv.SK_SRC_HOST, n=1001, lda=1001, m=1, k=1, ldy=1)) == 4096
+    for bad in (dict(k=0), dict(m=0), dict(n=0), dict(a_source=3), dict(ldy=4), dict(Y=None),
+                dict(a_source=sv.SK_SRC_SYNTH), dict(a_source=sv.SK_SRC_SYNTH, A=None, a_dtype=BF16),
+                dict(a_source=sv.SK_SRC_HOST, lda=100), dict(A=PA + 4), dict(a_dtype=FP8)):
+        assert fp(req(**bad)) == 0, bad
+
+
+def test_server_entry_points_reject_without_a_server():
+    L = sk.lib()
+    from paper_2603_20966_amd import serve as sv
+
+    sv._bind()
+    t = ctypes.c_int64(5)
+    r = sv.SkRequest()
+    assert L.sk_server_submit(None, ctypes.byref(r), ctypes.byref(t)) == EINVAL and t.value == 5
+    info = sv.SkTicketInfo()
+    assert L.sk_server_poll(None, 1, ctypes.byref(info)) == EINVAL
+    assert L.sk_server_wait(None, 1, 0.0, ctypes.byref(info)) == EINVAL
+    assert L.sk_server_cancel(None, 1) == EINVAL
+    assert L.sk_server_destroy(None) == EINVAL
+    h = ctypes.c_void_p()
+    for bad in ((1 << 20, 0, 4, 2), (1 << 20, 4, 0, 2), (1 << 20, 4, 17, 2), (1 << 20, 4, 4, 0),
+                (1 << 20, 4, 4, 9)):
+        assert L.sk_server_create(*bad, ctypes.byref(h)) == EINVAL and not h.value
+    assert L.sk_server_create(1 << 20, 4, 4, 2, None) == EINVAL

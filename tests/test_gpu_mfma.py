@@ -1,4 +1,4 @@
-"""GPU parity of the matrix-core path (FP32 A, k > 8): v_mfma_f32_16x16x4f32 over
+"""GPU parity of the matrix-core path (FP32 A, k > 16): v_mfma_f32_16x16x4f32 over
 2048-column strips, FP64 strip sums.
 
 Bars: relative Frobenius <= 1e-5 against the FP64 oracle, and element by element
@@ -40,9 +40,7 @@ def check(Y, A, seed, row0, col0, k, rel=1e-5):
 
 
 @pytest.mark.parametrize("m,n,k,row0,col0", [
-    (300, 5000, 9, 0, 0),       # smallest matrix-core sketch, ragged strips and rows
-    (300, 5000, 16, 5, 0),      # one 16-column tile
-    (300, 5000, 17, 0, 0),
+    (300, 5000, 17, 0, 0),      # smallest matrix-core sketch, ragged strips and rows
     (257, 4096, 64, 0, 0),      # two 2048 strips, one row past a 256-row tile
     (100, 2049, 33, 3, 1),      # unaligned Omega rows, one-column last strip
     (64, 3000, 128, 4097, 0),

@@ -43,8 +43,8 @@ def to_dev(x: np.ndarray) -> torch.Tensor:
 def chain(k: int) -> int:
     """Longest FP32 summation chain (+ tree depth) of the kernel that serves width k
     for FP32 A: at most 16 products per lane + 6 lane levels on the VALU path
-    (k <= 8; bound kept at 80), 2048 + 4 on the matrix-core path (k > 8)."""
-    return 80 if k <= 8 else 2052
+    (k <= 16; bound kept at 80), 2048 + 4 on the matrix-core path (k > 16)."""
+    return 80 if k <= 16 else 2052
 
 
 def check_fp32(Y: torch.Tensor, A: np.ndarray, seed, row0, col0, k, rel=1e-5):
