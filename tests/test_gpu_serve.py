@@ -8,7 +8,8 @@
   refused; queued requests can be cancelled; requests that arrive while others
   run are admitted before those finish.
 """
-import numpy as np
+import time
+
 import pytest
 import torch
 
@@ -136,19 +137,24 @@ def test_budget_admission_and_rejection():
 def test_overlap_of_late_arrivals():
     """Requests submitted while a long one runs are admitted (and launched on
     another stream) before it finishes."""
-    Ybig = torch.empty((16384, 5), device=DEV)
+    Ybig = torch.empty((32768, 5), device=DEV)
     small = [torch.empty((256, 5), device=DEV) for _ in range(3)]
     torch.cuda.synchronize()
-    with sk.SketchServer(2 << 30, max_slots=4, max_batch=4) as srv:
-        tb = srv.submit(sv.make_request(source=sv.SK_SRC_SYNTH, m=16384, n=16384, k=5, seed=2,
+    with sk.SketchServer(5 << 30, max_slots=4, max_batch=4) as srv:
+        tb = srv.submit(sv.make_request(source=sv.SK_SRC_SYNTH, m=32768, n=32768, k=5, seed=2,
                                         Y=Ybig), Ybig)
+        t_end = time.monotonic() + 30.0
+        while srv.poll(tb)["state"] == sv.SK_REQ_QUEUED and time.monotonic() < t_end:
+            pass
         ts = [srv.submit(sv.make_request(source=sv.SK_SRC_SYNTH, m=256, n=2048, k=5, seed=3 + i,
                                          Y=Y), Y) for i, Y in enumerate(small)]
         ib = srv.wait(tb, 60.0)
         infos = [srv.wait(t, 60.0) for t in ts]
     assert ib["state"] == sv.SK_REQ_DONE
     assert all(i["state"] == sv.SK_REQ_DONE for i in infos)
+    assert all(i["batch"] != ib["batch"] for i in infos)
     assert all(i["t_admit_us"] < ib["t_done_us"] for i in infos), (ib, infos)
+    assert min(i["t_done_us"] for i in infos) < ib["t_done_us"]   # they finished first
 
 
 def test_cancel_queued_request():
@@ -160,6 +166,9 @@ def test_cancel_queued_request():
     with sk.SketchServer(5 << 30, max_slots=1, max_batch=1) as srv:
         tb = srv.submit(sv.make_request(source=sv.SK_SRC_SYNTH, m=32768, n=32768, k=5, seed=2,
                                         Y=Ybig), Ybig)
+        t_end = time.monotonic() + 30.0
+        while srv.poll(tb)["state"] == sv.SK_REQ_QUEUED and time.monotonic() < t_end:
+            pass                                    # the worker admits it (about 1.5 ms of work)
         ts = [srv.submit(sv.make_request(source=sv.SK_SRC_SYNTH, m=256, n=2048, k=5, seed=3 + i,
                                          Y=Y), Y) for i, Y in enumerate(small)]
         cancelled = srv.cancel(ts[1])
