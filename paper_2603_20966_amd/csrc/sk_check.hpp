@@ -31,8 +31,8 @@ inline int check_common(int a_dtype, int64_t m, int64_t k, int64_t col0, const v
     if (Y == nullptr || ldy < k) return SK_EINVAL;
     if (((uintptr_t)Y & (y_dtype == SK_Y_F64 ? 7u : 3u)) != 0) return SK_EALIGN;
     // grid: rows per workgroup are at most 1024 (streaming kernel) or exactly
-    // 256 (matrix-core kernel), row blocks at most 65535
-    if (m > kMaxGridY * (sk::use_mfma(a_dtype, k) ? 256 : 1024)) return SK_EUNSUPPORTED;
+    // kMfmaRows (matrix-core kernel), row blocks at most 65535
+    if (m > kMaxGridY * (sk::use_mfma(a_dtype, k) ? sk::kMfmaRows : 1024)) return SK_EUNSUPPORTED;
     return SK_OK;
 }
 

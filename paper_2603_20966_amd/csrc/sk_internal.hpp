@@ -34,7 +34,7 @@ constexpr int strip_width(int kclass, int adtype) {
 // 4.1 TB/s on VALU, 2.9 TB/s with one 16-column matrix-core tile).  Its strips
 // are 2048 columns.
 constexpr int kMfmaStrip = 2048;
-constexpr int kMfmaRows = 256;     // rows of a matrix-core tile
+constexpr int kMfmaRows = 512;     // rows of a matrix-core tile
 constexpr int kMfmaMinK = kColGroup + 1;
 constexpr bool use_mfma(int adtype, int64_t k) { return adtype == 0 && k >= kMfmaMinK; }
 

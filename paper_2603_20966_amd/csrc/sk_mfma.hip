@@ -1,25 +1,30 @@
 // Matrix-core kernel for Y = A * Omega(seed) with a wide sketch (k > 16) on gfx950.
 //
 // Once k is large the product is a dense contraction (2k flops per A element;
-// non-packed FP32 VALU FMAs reach their ridge near k = 20, and above k ~ 8
-// they already take most issue slots at HBM speed), so the local
+// non-packed FP32 VALU FMAs reach their ridge near k = 20), so the local
 // multiplication of Alg. 1 runs on the MFMA units: v_mfma_f32_16x16x4f32,
 // FP32 in, FP32 accumulate.
 //
-// Tile of one workgroup (256 threads = 4 waves): 256 rows of A x a strip of
+// Tile of one workgroup (512 threads = 8 waves): 512 rows of A x a strip of
 // kMfmaStrip contraction columns x BN = 16*NT sketch columns.  Each wave owns
-// 64 rows (4 M-tiles of 16) x NT N-tiles, i.e. 4*NT accumulator tiles.
+// 64 rows (4 M-tiles of 16) x NT N-tiles, i.e. 4*NT accumulator tiles.  Eight
+// waves share each generated Omega chunk, which halves the generation work per
+// A element against four (measured: 109 vs 75 TFLOP/s at k = 256).
 //
-// Contraction in chunks of 16 columns:
+// Contraction in chunks of KC columns (32, or 16 when NT = 8 fills the
+// registers):
 //   * A goes straight from HBM into the MFMA A-operand layout: lane (g, i)
-//     (g = lane/16, i = lane%16) loads the 16 bytes A[row i][kc+4g .. kc+4g+3]
-//     of each M-tile; component s feeds MFMA s, whose contraction index g then
-//     stands for column kc+4g+s.  Any order of the contraction is a valid
-//     product, so no shuffle is needed.
-//   * Omega for the chunk (16 x BN) is generated from the seed into one half of
-//     a double-buffered LDS tile, laid out [column][16 + 4 pad] so that lane
-//     (g, j) reads Omega[kc+4g .. kc+4g+3][j] as one conflict-free
-//     ds_read_b128: exactly the B operands of the same four MFMAs.
+//     (g = lane/16, i = lane%16) loads the KC/4 contiguous floats
+//     A[row i][kc + g*KC/4 ...] of each M-tile as KC/16 back-to-back 16-byte
+//     loads, so each 128-byte line of a row is requested at once; component s of
+//     load v feeds one MFMA, whose contraction index g then stands for column
+//     kc + g*KC/4 + 4v + s.  Any order of the contraction is a valid product, so
+//     no shuffle is needed.  Plain (temporal) loads: the lines of a row are
+//     shared by the four lanes of a row (measured faster than nontemporal).
+//   * Omega for the chunk (KC x BN) is generated from the seed into one half of
+//     a double-buffered LDS tile, laid out [column][KC + 4 pad] so that lane
+//     (g, j) reads Omega[kc + g*KC/4 ...][j] as ds_read_b128s: exactly the B
+//     operands of the same MFMAs.
 //   * The next chunk's Omega is generated while this chunk's MFMAs run (VALU
 //     and matrix cores work in parallel); one LDS-only barrier per chunk.
 // Strip partials are FP32 in [S][m][k]; the FP64 strip sum is the shared
@@ -38,11 +43,14 @@ namespace {
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 
-constexpr int kTM = 4;        // M-tiles (16 rows) per wave
-constexpr int kBM = 4 * kTM * 16;   // rows per workgroup
+constexpr int kTM = 4;                  // M-tiles (16 rows) per wave
+constexpr int kWaves = 8;               // waves per workgroup
+constexpr int kThreads = 64 * kWaves;
+constexpr int kBM = kWaves * kTM * 16;  // rows per workgroup
 static_assert(kBM == kMfmaRows, "tile rows");
-constexpr int kKC = 16;       // contraction columns per chunk
-constexpr int kLdsRow = 20;   // floats per LDS column (16 + 4 pad)
+// contraction columns per chunk, and floats per LDS column (chunk + 4 pad)
+constexpr int chunk_cols(int nt) { return nt >= 8 ? 16 : 32; }
+constexpr int lds_row(int nt) { return chunk_cols(nt) + 4; }
 
 struct MArgs {
     int64_t m;
@@ -67,7 +75,7 @@ __device__ __forceinline__ void lds_barrier_m() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// One tile: rows [row_base, row_base + 256) of a block, one strip of its
+// One tile: rows [block_row, block_row + 512) of a block, one strip of its
 // columns, sketch columns [n_base, n_base + 16*NT).
 struct MTile {
     const unsigned char* A;   // the block's A
@@ -89,8 +97,11 @@ struct MTile {
 };
 
 template <int NT, bool GEN>
-__device__ __forceinline__ void mfma_tile(const MTile& t, float (*om)[16 * NT][kLdsRow]) {
+__device__ __forceinline__ void mfma_tile(const MTile& t, float (*om)[16 * NT][lds_row(NT)]) {
     constexpr int BN = 16 * NT;
+    constexpr int kKC = chunk_cols(NT);
+    constexpr int kLdsRow = lds_row(NT);
+    constexpr int kLV = kKC / 16;   // 16-byte A loads per lane per M-tile per chunk
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
@@ -109,29 +120,33 @@ __device__ __forceinline__ void mfma_tile(const MTile& t, float (*om)[16 * NT][k
 #pragma unroll
     for (int tm = 0; tm < kTM; ++tm) {
         const int64_t r = min<int64_t>(row_base + tm * 16 + i16, t.m - 1);
-        arow[tm] = t.A + r * lda4 + (t.col_begin + 4 * g) * 4;
+        arow[tm] = t.A + r * lda4 + (t.col_begin + 4 * kLV * g) * 4;
     }
-    auto load_a = [&](v4f* a, int c) {
+    auto load_a = [&](v4f (*a)[kLV], int c) {
         if (c >= nchunks) return;
-        const int kl = c * kKC + 4 * g;               // local column of component 0
+        const int kl = c * kKC + 4 * kLV * g;               // local column of component 0
 #pragma unroll
         for (int tm = 0; tm < kTM; ++tm) {
             const unsigned char* p = arow[tm] + (int64_t)c * kKC * 4;
-            if (kl + 3 < w) {
-                a[tm] = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(p));
+            if (kl + 4 * kLV - 1 < w) {
+#pragma unroll
+                for (int v = 0; v < kLV; ++v) a[tm][v] = *reinterpret_cast<const v4f*>(p + 16 * v);
             } else {
-                v4f v = {0.f, 0.f, 0.f, 0.f};
                 const float* pf = reinterpret_cast<const float*>(p);
-                for (int e = 0; e < 4; ++e)
-                    if (kl + e < w) v[e] = pf[e];
-                a[tm] = v;
+#pragma unroll
+                for (int v = 0; v < kLV; ++v) {
+                    v4f x = {0.f, 0.f, 0.f, 0.f};
+                    for (int e = 0; e < 4; ++e)
+                        if (kl + 4 * v + e < w) x[e] = pf[4 * v + e];
+                    a[tm][v] = x;
+                }
             }
         }
     };
 
     // ---- Omega chunk -> LDS ----------------------------------------------------------
     // zero the columns past k once: generation never writes them
-    for (int it = tid; it < 2 * BN * kLdsRow; it += 256) {
+    for (int it = tid; it < 2 * BN * kLdsRow; it += kThreads) {
         const int n = (it / kLdsRow) % BN;
         if (n >= kb) (&om[0][0][0])[it] = 0.0f;
     }
@@ -141,9 +156,9 @@ __device__ __forceinline__ void mfma_tile(const MTile& t, float (*om)[16 * NT][k
         if constexpr (GEN) {
             const int64_t g0 = t.row0 + t.col_begin + (int64_t)c * kKC;  // global Omega row of local 0
             const int64_t q_lo = g0 >> 2;
-            const int nq = (int)(((g0 + kKC - 1) >> 2) - q_lo + 1);       // 4, or 5 if unaligned
+            const int nq = (int)(((g0 + kKC - 1) >> 2) - q_lo + 1);       // KC/4, or one more if unaligned
             const int items = nq * kb;
-            for (int it = tid; it < items; it += 256) {
+            for (int it = tid; it < items; it += kThreads) {
                 const int qi = it / kb;
                 const int n = it - qi * kb;
                 const float4 z = omega4((uint64_t)(q_lo + qi), t.col0 + (uint32_t)(n_base + n),
@@ -161,7 +176,7 @@ __device__ __forceinline__ void mfma_tile(const MTile& t, float (*om)[16 * NT][k
                 }
             }
         } else {
-            for (int it = tid; it < kKC * kb; it += 256) {
+            for (int it = tid; it < kKC * kb; it += kThreads) {
                 const int kl = it / kb;
                 const int n = it - kl * kb;
                 om[buf][n][kl] = (kl < kvalid)
@@ -177,26 +192,31 @@ __device__ __forceinline__ void mfma_tile(const MTile& t, float (*om)[16 * NT][k
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) acc[tm][nt] = v4f{0.f, 0.f, 0.f, 0.f};
 
-    v4f a0[kTM], a1[kTM];
+    v4f a0[kTM][kLV], a1[kTM][kLV];
     load_a(a0, 0);
     load_a(a1, 1);
     make_chunk(0);
     lds_barrier_m();
 
-    auto compute = [&](const v4f* a, int c) {
+    auto compute = [&](v4f (*a)[kLV], int c) {
         const int buf = c & 1;
-        v4f bop[NT];
+        v4f bop[NT][kLV];
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt)
-            bop[nt] = *reinterpret_cast<const v4f*>(&om[buf][nt * 16 + i16][4 * g]);
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
+            for (int v = 0; v < kLV; ++v)
+                bop[nt][v] =
+                    *reinterpret_cast<const v4f*>(&om[buf][nt * 16 + i16][4 * kLV * g + 4 * v]);
 #pragma unroll
-            for (int tm = 0; tm < kTM; ++tm)
+        for (int v = 0; v < kLV; ++v)
 #pragma unroll
-                for (int nt = 0; nt < NT; ++nt)
-                    acc[tm][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[tm][s], bop[nt][s],
-                                                                        acc[tm][nt], 0, 0, 0);
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int tm = 0; tm < kTM; ++tm)
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt)
+                        acc[tm][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                            a[tm][v][s], bop[nt][v][s], acc[tm][nt], 0, 0, 0);
     };
 
     for (int c = 0; c < nchunks; c += 2) {
@@ -245,10 +265,10 @@ __device__ __forceinline__ void mfma_tile(const MTile& t, float (*om)[16 * NT][k
     }
 }
 
-// One call: grid (strips of all blocks, 256-row tiles, sketch-column blocks).
+// One call: grid (strips of all blocks, 512-row tiles, sketch-column blocks).
 template <int NT, bool GEN>
-__global__ __launch_bounds__(256) void k_gemm_mfma(const MArgs args) {
-    __shared__ float om[2][16 * NT][kLdsRow];
+__global__ __launch_bounds__(kThreads) void k_gemm_mfma(const MArgs args) {
+    __shared__ float om[2][16 * NT][lds_row(NT)];
     const int strip = blockIdx.x;
     int b = 0;
     int64_t sib = strip;
@@ -288,8 +308,8 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(const MArgs args) {
 // ones a call for that request alone would run, walked by a fixed grid in an
 // XCD-grouped order, so each result does not depend on the batch.
 template <int NT>
-__global__ __launch_bounds__(256) void k_gemm_mfma_batch(const BatchArgs args) {
-    __shared__ float om[2][16 * NT][kLdsRow];
+__global__ __launch_bounds__(kThreads) void k_gemm_mfma_batch(const BatchArgs args) {
+    __shared__ float om[2][16 * NT][lds_row(NT)];
     const int64_t T8 = (args.total_tiles + 7) / 8;
     bool first = true;
     for (int64_t v = blockIdx.x; v < 8 * T8; v += gridDim.x) {   // gridDim.x is a multiple of 8
@@ -333,7 +353,7 @@ __global__ __launch_bounds__(256) void k_gemm_mfma_batch(const BatchArgs args) {
 
 template <int NT, bool GEN>
 hipError_t launch_m(const MArgs& a, dim3 grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_gemm_mfma<NT, GEN>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_gemm_mfma<NT, GEN>), grid, dim3(kThreads), 0, s, a);
     return hipGetLastError();
 }
 
@@ -392,13 +412,13 @@ template <int NT>
 hipError_t run_mfma_batch(const BatchArgs& a, int grid, hipStream_t s) {
     static const int per_cu = [] {
         int n = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gemm_mfma_batch<NT>, 256, 0) !=
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gemm_mfma_batch<NT>, kThreads, 0) !=
             hipSuccess)
             n = 1;
         return n;
     }();
     grid = batch_grid(per_cu, a.total_tiles, grid);
-    hipLaunchKernelGGL((k_gemm_mfma_batch<NT>), dim3((unsigned)grid), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_gemm_mfma_batch<NT>), dim3((unsigned)grid), dim3(kThreads), 0, s, a);
     return hipGetLastError();
 }
 

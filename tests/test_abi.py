@@ -73,7 +73,7 @@ def gm(A=PA, adt=F32, m=64, n=1024, lda=1024, scales=None, seed=1, row0=0, col0=
     (dict(adt=BF16, lda=1028, n=1028), EALIGN),          # 1028*2 % 16 != 0
     (dict(ws=None), EWS), (dict(wsb=16), EWS), (dict(ws=PW + 8), EALIGN),
     (dict(m=70_000_000), EUNSUP),
-    (dict(m=20_000_000, k=64, ldy=64), EUNSUP),           # matrix-core grid limit
+    (dict(m=40_000_000, k=64, ldy=64), EUNSUP),           # matrix-core grid limit (65535 x 512 rows)
 ])
 def test_gen_matmul_rejects(kw, expect):
     args = dict(n=4096, lda=4096)

@@ -41,7 +41,9 @@ def check(Y, A, seed, row0, col0, k, rel=1e-5):
 
 @pytest.mark.parametrize("m,n,k,row0,col0", [
     (300, 5000, 17, 0, 0),      # smallest matrix-core sketch, ragged strips and rows
-    (257, 4096, 64, 0, 0),      # two 2048 strips, one row past a 256-row tile
+    (257, 4096, 64, 0, 0),      # two 2048 strips, one partial 512-row tile
+    (513, 4100, 64, 0, 0),      # one row past a 512-row tile, ragged third strip
+    (1100, 2100, 256, 3, 0),    # 16-column chunks (8 N-tiles), three row tiles
     (100, 2049, 33, 3, 1),      # unaligned Omega rows, one-column last strip
     (64, 3000, 128, 4097, 0),
     (70, 2500, 129, 1, 5),      # two column blocks, ragged last one
