@@ -199,9 +199,14 @@ def run_precision(args):
             Y = torch.empty((N, k), device=dev)
             t, _ = _timeit(torch, stream, lambda: sk.sketch_gen_matmul(Aq, 1, k, Y=Y, a_scales=sc,
                                                                        stream=stream), args.steps)
+            on_mc = kind == "fp8" or k > 16
+            flops = 2 * N * N * 16 * -(-k // 16) * 2      # hi + lo BF16 terms, padded N-tiles
             rows.append({"a_dtype": kind, "k": k, "ms": round(t, 4),
+                         "kernel": ("BF16 matrix cores (v_mfma_f32_16x16x32_bf16, Omega hi+lo)"
+                                    if on_mc else "VALU FMA"),
                          "A_GBps": round(N * N * esz / (t * 1e-3) / 1e9, 1),
-                         "frac_hbm": round(N * N * esz / (t * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)})
+                         "frac_hbm": round(N * N * esz / (t * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                         "mfma_TFLOPs_issued": round(flops / (t * 1e-3) / 1e12, 1) if on_mc else None})
         del Aq
     out = {"metric": "A-stream GB/s, Y=A*Omega(seed), A stored in FP32 / BF16 / FP8-E4M3",
            "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "higher_is_better": True,

@@ -48,8 +48,9 @@ int run_product(sk::GemmLaunch& g, int64_t n_total) {
         if (t.end) (void)hipEventRecord(t.end, g.stream);
         return SK_OK;
     }
-    return from_hip(sk::use_mfma(g.adtype, g.k) ? sk::launch_gemm_mfma(g)
-                                                 : sk::launch_gemm_stream(g));
+    if (sk::use_mfma(g.adtype, g.k)) return from_hip(sk::launch_gemm_mfma(g));
+    if (sk::use_mfma_lp(g.adtype, g.k)) return from_hip(sk::launch_gemm_mfma_lp(g));
+    return from_hip(sk::launch_gemm_stream(g));
 }
 
 }  // namespace

@@ -30,9 +30,12 @@ inline int check_common(int a_dtype, int64_t m, int64_t k, int64_t col0, const v
     if (m == 0 || k == 0) return SK_OK;
     if (Y == nullptr || ldy < k) return SK_EINVAL;
     if (((uintptr_t)Y & (y_dtype == SK_Y_F64 ? 7u : 3u)) != 0) return SK_EALIGN;
-    // grid: rows per workgroup are at most 1024 (streaming kernel) or exactly
-    // kMfmaRows (matrix-core kernel), row blocks at most 65535
-    if (m > kMaxGridY * (sk::use_mfma(a_dtype, k) ? sk::kMfmaRows : 1024)) return SK_EUNSUPPORTED;
+    // grid: rows per workgroup are at most 1024 (streaming kernel), exactly
+    // kMfmaRows (FP32 matrix-core kernel) or at least 256 (low-precision
+    // matrix-core kernel); row blocks at most 65535
+    const int64_t rows = sk::use_mfma(a_dtype, k) ? sk::kMfmaRows
+                         : sk::use_mfma_lp(a_dtype, k) ? 256 : 1024;
+    if (m > kMaxGridY * rows) return SK_EUNSUPPORTED;
     return SK_OK;
 }
 

@@ -38,10 +38,23 @@ constexpr int kMfmaRows = 512;     // rows of a matrix-core tile
 constexpr int kMfmaMinK = kColGroup + 1;
 constexpr bool use_mfma(int adtype, int64_t k) { return adtype == 0 && k >= kMfmaMinK; }
 
+// Low-precision A on the BF16 matrix cores: FP8 at every k (on the VALU path
+// its conversions and 5 FMAs per byte cap k = 5 at 2.6 TB/s, against 3.2 TB/s
+// here), BF16 past one column group (at k = 5 both paths measured the same
+// speed, and the VALU path sums with FP32 Omega: 1e-7 against 2.5e-6 relative
+// arithmetic error).  Strips of 4096 columns.
+constexpr int kLpStrip = 4096;
+constexpr int kLpBatchWaves = 8;                  // waves per tile in batched launches
+constexpr int kLpBatchRows = 64 * kLpBatchWaves;  // rows per tile in batched launches
+constexpr bool use_mfma_lp(int adtype, int64_t k) {
+    return adtype == 2 || (adtype == 1 && k > kColGroup);
+}
+
 // Strip width used for a sketch of width k with A stored as adtype.
 constexpr int64_t strip_width_for(int adtype, int64_t k) {
-    return use_mfma(adtype, k) ? kMfmaStrip
-                               : strip_width(k_class((int)(k < kColGroup ? k : kColGroup)), adtype);
+    return use_mfma(adtype, k)      ? kMfmaStrip
+           : use_mfma_lp(adtype, k) ? kLpStrip
+                                    : strip_width(k_class((int)(k < kColGroup ? k : kColGroup)), adtype);
 }
 
 struct BlockDesc {
@@ -116,6 +129,12 @@ hipError_t launch_gemm_mfma(const GemmLaunch& g);
 // count nt; BatchReq.rowblocks counts kMfmaRows-row tiles, strips kMfmaStrip columns.
 hipError_t launch_gemm_mfma_batch(const BatchArgs& a, int nt, int grid, hipStream_t s);
 int mfma_ntiles(int64_t k);
+// Low-precision A (BF16 / FP8) on the BF16 matrix cores; batches use
+// kLpBatchRows-row tiles and kLpStrip-column strips.
+hipError_t launch_gemm_mfma_lp(const GemmLaunch& g);
+hipError_t launch_gemm_mfma_lp_batch(const BatchArgs& a, int nt, int adtype, int grid,
+                                     hipStream_t s);
+int lp_ntiles(int64_t k);
 // Persistent grid for total_tiles tiles of a kernel holding per_cu workgroups
 // per compute unit (grid > 0: that size, capped at the tile count); a
 // multiple of 8.

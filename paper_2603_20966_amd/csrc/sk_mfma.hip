@@ -96,6 +96,44 @@ struct MTile {
     bool single;
 };
 
+// Write a wave's accumulators: lane (g, j) holds rows 4g..4g+3 and column j of
+// each 16 x 16 tile.  The per-128-row scale (FP8 storage) is applied to each
+// strip partial; a single-strip call writes Y directly (old Y added in FP64).
+template <int NT>
+__device__ __forceinline__ void store_tile(const MTile& t, const v4f (&acc)[kTM][NT],
+                                           int64_t row_base, int kb, int g, int i16) {
+#pragma unroll
+    for (int tm = 0; tm < kTM; ++tm) {
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const int cn = nt * 16 + i16;
+            if (cn >= kb) continue;
+            const int64_t col = t.n_base + cn;
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                const int64_t r = row_base + tm * 16 + 4 * g + rr;
+                if (r >= t.m) continue;
+                float v = acc[tm][nt][rr];
+                if (t.scales) v *= t.scales[r >> 7];
+                if (t.single) {
+                    double y = (double)v;
+                    if (t.y_f64) {
+                        double* Yp = static_cast<double*>(t.Y) + r * t.ldy + col;
+                        if (t.beta) y += *Yp;
+                        *Yp = y;
+                    } else {
+                        float* Yp = static_cast<float*>(t.Y) + r * t.ldy + col;
+                        if (t.beta) y += (double)*Yp;
+                        *Yp = (float)y;
+                    }
+                } else {
+                    t.partials[(t.strip * t.m + r) * t.k + col] = v;
+                }
+            }
+        }
+    }
+}
+
 template <int NT, bool GEN>
 __device__ __forceinline__ void mfma_tile(const MTile& t, float (*om)[16 * NT][lds_row(NT)]) {
     constexpr int BN = 16 * NT;
@@ -232,37 +270,7 @@ __device__ __forceinline__ void mfma_tile(const MTile& t, float (*om)[16 * NT][l
         }
     }
 
-    // ---- write: lane (g, j) holds rows 4g..4g+3, column j of each tile ----------------
-#pragma unroll
-    for (int tm = 0; tm < kTM; ++tm) {
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-            const int cn = nt * 16 + i16;
-            if (cn >= kb) continue;
-            const int64_t col = n_base + cn;
-#pragma unroll
-            for (int rr = 0; rr < 4; ++rr) {
-                const int64_t r = row_base + tm * 16 + 4 * g + rr;
-                if (r >= t.m) continue;
-                float v = acc[tm][nt][rr];
-                if (t.scales) v *= t.scales[r >> 7];
-                if (t.single) {
-                    double y = (double)v;
-                    if (t.y_f64) {
-                        double* Yp = static_cast<double*>(t.Y) + r * t.ldy + col;
-                        if (t.beta) y += *Yp;
-                        *Yp = y;
-                    } else {
-                        float* Yp = static_cast<float*>(t.Y) + r * t.ldy + col;
-                        if (t.beta) y += (double)*Yp;
-                        *Yp = (float)y;
-                    }
-                } else {
-                    t.partials[(t.strip * t.m + r) * t.k + col] = v;
-                }
-            }
-        }
-    }
+    store_tile<NT>(t, acc, row_base, kb, g, i16);
 }
 
 // One call: grid (strips of all blocks, 512-row tiles, sketch-column blocks).
@@ -351,6 +359,320 @@ __global__ __launch_bounds__(kThreads) void k_gemm_mfma_batch(const BatchArgs ar
     }
 }
 
+// ---------------------------------------------------------------------------
+// Low-precision A (BF16, or FP8-E4M3 widened to BF16 exactly) on the BF16
+// matrix cores: v_mfma_f32_16x16x32_bf16, FP32 accumulate.  Omega is split into
+// two BF16 terms, hi = bf16(w) and lo = bf16(w - hi), and each step runs two
+// MFMAs (A*hi, then A*lo): |w - hi - lo| <= 2^-16 |w|, far below the storage
+// error of A, so the product carries A's quantisation only.  The workgroup
+// is W waves x 64 rows sharing each generated Omega chunk (64 contraction
+// columns): the more rows, the less generation per A element, which matters
+// because a byte of FP8 holds four times the elements of a byte of FP32.
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+constexpr int kLpKC = 64;            // contraction columns per chunk
+constexpr int kLpRow = kLpKC + 8;    // bf16 per LDS column (chunk + 8 pad)
+static_assert(64 * kLpBatchWaves == kLpBatchRows, "batch tile rows");
+
+__device__ __forceinline__ uint32_t bf16_rne_bits(float x) {
+    const uint32_t u = __float_as_uint(x);
+    return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+
+// Omega value -> (hi, lo) BF16 bit patterns; z - hi is exact in FP32.
+__device__ __forceinline__ void split_bf16(float z, uint16_t& hi, uint16_t& lo) {
+    const uint32_t h = bf16_rne_bits(z);
+    hi = (uint16_t)h;
+    lo = (uint16_t)bf16_rne_bits(z - __uint_as_float(h << 16));
+}
+
+// 4 FP8-E4M3 codes (one word) -> 4 BF16 in two words (exact: 4 significant bits).
+__device__ __forceinline__ void fp8x4_to_bf16(uint32_t w, uint32_t& lo2, uint32_t& hi2) {
+    const auto a = __builtin_amdgcn_cvt_pk_f32_fp8((int)w, false);
+    const auto b = __builtin_amdgcn_cvt_pk_f32_fp8((int)w, true);
+    lo2 = (__float_as_uint(a[1]) & 0xFFFF0000u) | (__float_as_uint(a[0]) >> 16);
+    hi2 = (__float_as_uint(b[1]) & 0xFFFF0000u) | (__float_as_uint(b[0]) >> 16);
+}
+
+template <int NT, int ADT, int W, bool GEN>
+__device__ __forceinline__ void lp_tile(const MTile& t, uint16_t (*oh)[16 * NT][kLpRow],
+                                        uint16_t (*ol)[16 * NT][kLpRow]) {
+    constexpr int BN = 16 * NT;
+    constexpr int TH = 64 * W;
+    constexpr int es = ADT == 1 ? 2 : 1;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int g = lane >> 4;
+    const int i16 = lane & 15;
+
+    const int w = (int)min<int64_t>(kLpStrip, t.n - t.col_begin);
+    const int nchunks = (w + kLpKC - 1) / kLpKC;
+    const int64_t row_base = t.block_row + wave * (kTM * 16);
+    const int kb = (int)min<int64_t>(BN, t.k - t.n_base);
+
+    // ---- A: lane (g, i) holds columns kc + 16g .. kc + 16g + 15 of row i --------
+    const int64_t ldab = t.lda * es;
+    const unsigned char* arow[kTM];
+#pragma unroll
+    for (int tm = 0; tm < kTM; ++tm) {
+        const int64_t r = min<int64_t>(row_base + tm * 16 + i16, t.m - 1);
+        arow[tm] = t.A + r * ldab + (t.col_begin + 16 * g) * es;
+    }
+    // raw A of a chunk: 32 bytes (BF16) or 16 bytes (FP8) per lane and M-tile;
+    // FP8 is widened to BF16 only when the chunk is consumed, so the loads stay
+    // in flight behind the current chunk's MFMAs
+    constexpr int RW = ADT == 1 ? 2 : 1;
+    auto load_a = [&](v4u (*a)[RW], int c) {
+        if (c >= nchunks) return;
+        const int kl = c * kLpKC + 16 * g;
+#pragma unroll
+        for (int tm = 0; tm < kTM; ++tm) {
+            const unsigned char* p = arow[tm] + (int64_t)c * kLpKC * es;
+            if (kl + 15 < w) {
+#pragma unroll
+                for (int v = 0; v < RW; ++v) a[tm][v] = *reinterpret_cast<const v4u*>(p + 16 * v);
+            } else {
+                uint32_t wd[4 * RW];
+#pragma unroll
+                for (int q = 0; q < 4 * RW; ++q) wd[q] = 0u;
+                for (int e = 0; e < 16; ++e) {
+                    if (kl + e < w) {
+                        const uint32_t v = ADT == 1 ? (uint32_t)reinterpret_cast<const uint16_t*>(p)[e]
+                                                    : (uint32_t)p[e];
+                        const int byte = e * es;
+                        wd[byte >> 2] |= v << (8 * (byte & 3));
+                    }
+                }
+#pragma unroll
+                for (int v = 0; v < RW; ++v)
+                    a[tm][v] = v4u{wd[4 * v], wd[4 * v + 1], wd[4 * v + 2], wd[4 * v + 3]};
+            }
+        }
+    };
+    // the two 8-element BF16 operands of an M-tile
+    auto operands = [&](const v4u* raw, v4u* op) {
+        if constexpr (ADT == 1) {
+            op[0] = raw[0];
+            op[1] = raw[1];
+        } else {
+            uint32_t o[8];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) fp8x4_to_bf16(raw[0][q], o[2 * q], o[2 * q + 1]);
+            op[0] = v4u{o[0], o[1], o[2], o[3]};
+            op[1] = v4u{o[4], o[5], o[6], o[7]};
+        }
+    };
+
+    // ---- Omega chunk -> LDS as (hi, lo) ------------------------------------------
+    for (int it = tid; it < 2 * BN * kLpRow; it += TH) {
+        const int n = (it / kLpRow) % BN;
+        if (n >= kb) {
+            (&oh[0][0][0])[it] = 0;
+            (&ol[0][0][0])[it] = 0;
+        }
+    }
+    auto make_chunk = [&](int c) {
+        const int buf = c & 1;
+        const int kvalid = min(kLpKC, w - c * kLpKC);
+        if constexpr (GEN) {
+            const int64_t g0 = t.row0 + t.col_begin + (int64_t)c * kLpKC;
+            const int64_t q_lo = g0 >> 2;
+            const int nq = (int)(((g0 + kLpKC - 1) >> 2) - q_lo + 1);
+            const int items = nq * kb;
+            for (int it = tid; it < items; it += TH) {
+                const int qi = it / kb;
+                const int n = it - qi * kb;
+                const float4 z = omega4((uint64_t)(q_lo + qi), t.col0 + (uint32_t)(t.n_base + n),
+                                        t.key0, t.key1);
+                const int kl0 = (int)(4 * (q_lo + qi) - g0);
+                const float zz[4] = {z.x, z.y, z.z, z.w};
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int kl = kl0 + u;
+                    if (kl >= 0 && kl < kLpKC) {
+                        uint16_t h = 0, l = 0;
+                        if (kl < kvalid) split_bf16(zz[u], h, l);
+                        oh[buf][n][kl] = h;
+                        ol[buf][n][kl] = l;
+                    }
+                }
+            }
+        } else {
+            for (int it = tid; it < kLpKC * kb; it += TH) {
+                const int kl = it / kb;
+                const int n = it - kl * kb;
+                uint16_t h = 0, l = 0;
+                if (kl < kvalid)
+                    split_bf16(t.omega[(t.col_begin + (int64_t)c * kLpKC + kl) * t.ldo + t.n_base + n],
+                               h, l);
+                oh[buf][n][kl] = h;
+                ol[buf][n][kl] = l;
+            }
+        }
+    };
+
+    v4f acc[kTM][NT];
+#pragma unroll
+    for (int tm = 0; tm < kTM; ++tm)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[tm][nt] = v4f{0.f, 0.f, 0.f, 0.f};
+
+    v4u a0[kTM][RW], a1[kTM][RW];
+    load_a(a0, 0);
+    load_a(a1, 1);
+    make_chunk(0);
+    lds_barrier_m();
+
+    auto compute = [&](v4u (*a)[RW], int c) {
+        const int buf = c & 1;
+        v4u op[kTM][2];
+#pragma unroll
+        for (int tm = 0; tm < kTM; ++tm) operands(a[tm], op[tm]);
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                const v4u bh = *reinterpret_cast<const v4u*>(&oh[buf][nt * 16 + i16][16 * g + 8 * v]);
+                const v4u bl = *reinterpret_cast<const v4u*>(&ol[buf][nt * 16 + i16][16 * g + 8 * v]);
+#pragma unroll
+                for (int tm = 0; tm < kTM; ++tm) {
+                    const v8bf av = __builtin_bit_cast(v8bf, op[tm][v]);
+                    acc[tm][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        av, __builtin_bit_cast(v8bf, bh), acc[tm][nt], 0, 0, 0);
+                    acc[tm][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        av, __builtin_bit_cast(v8bf, bl), acc[tm][nt], 0, 0, 0);
+                }
+            }
+        }
+    };
+
+    for (int c = 0; c < nchunks; c += 2) {
+        if (c + 1 < nchunks) make_chunk(c + 1);
+        compute(a0, c);
+        load_a(a0, c + 2);
+        lds_barrier_m();
+        if (c + 1 < nchunks) {
+            if (c + 2 < nchunks) make_chunk(c + 2);
+            compute(a1, c + 1);
+            load_a(a1, c + 3);
+            lds_barrier_m();
+        }
+    }
+    store_tile<NT>(t, acc, row_base, kb, g, i16);
+}
+
+// One call: grid (strips of all blocks, 64W-row tiles, sketch-column blocks).
+template <int NT, int ADT, int W, bool GEN>
+__global__ __launch_bounds__(64 * W) void k_gemm_mfma_lp(const MArgs args) {
+    __shared__ uint16_t oh[2][16 * NT][kLpRow];
+    __shared__ uint16_t ol[2][16 * NT][kLpRow];
+    const int strip = blockIdx.x;
+    int b = 0;
+    int64_t sib = strip;
+    for (; b < args.P; ++b) {
+        const int64_t sb = (args.blk[b].n + kLpStrip - 1) / kLpStrip;
+        if (sib < sb) break;
+        sib -= sb;
+    }
+    const BlockDesc& blk = args.blk[b];
+    MTile t;
+    t.A = static_cast<const unsigned char*>(blk.A);
+    t.lda = blk.lda;
+    t.n = blk.n;
+    t.row0 = blk.row0;
+    t.scales = blk.scales;
+    t.m = args.m;
+    t.k = args.k;
+    t.col_begin = sib * kLpStrip;
+    t.block_row = (int64_t)blockIdx.y * (64 * W);
+    t.n_base = blockIdx.z * 16 * NT;
+    t.key0 = args.key0;
+    t.key1 = args.key1;
+    t.col0 = args.col0;
+    t.omega = args.omega;
+    t.ldo = args.ldo;
+    t.Y = args.Y;
+    t.ldy = args.ldy;
+    t.y_f64 = args.y_f64;
+    t.beta = args.beta;
+    t.partials = args.partials;
+    t.strip = strip;
+    t.single = (args.S_total == 1);
+    lp_tile<NT, ADT, W, GEN>(t, oh, ol);
+}
+
+// Batch of requests of one class (serving); rows per tile = kLpBatchRows.
+template <int NT, int ADT>
+__global__ __launch_bounds__(64 * kLpBatchWaves) void k_gemm_mfma_lp_batch(const BatchArgs args) {
+    __shared__ uint16_t oh[2][16 * NT][kLpRow];
+    __shared__ uint16_t ol[2][16 * NT][kLpRow];
+    const int64_t T8 = (args.total_tiles + 7) / 8;
+    bool first = true;
+    for (int64_t v = blockIdx.x; v < 8 * T8; v += gridDim.x) {   // gridDim.x is a multiple of 8
+        const int64_t tt = (v % 8) * T8 + v / 8;
+        if (tt >= args.total_tiles) continue;
+        int q = 0;
+        while (q + 1 < args.count && tt >= args.req[q + 1].tile_begin) ++q;
+        const BatchReq& rq = args.req[q];
+        const int64_t lt = tt - rq.tile_begin;
+        const int64_t strip = lt % rq.strips;
+        const int64_t rb = (lt / rq.strips) % rq.rowblocks;
+        const int nb = (int)(lt / ((int64_t)rq.strips * rq.rowblocks));
+        MTile t;
+        t.A = static_cast<const unsigned char*>(rq.A);
+        t.lda = rq.lda;
+        t.n = rq.n;
+        t.row0 = rq.row0;
+        t.scales = rq.scales;
+        t.m = rq.m;
+        t.k = rq.k;
+        t.col_begin = strip * kLpStrip;
+        t.block_row = rb * kLpBatchRows;
+        t.n_base = nb * 16 * NT;
+        t.key0 = (uint32_t)rq.seed;
+        t.key1 = (uint32_t)(rq.seed >> 32);
+        t.col0 = rq.col0;
+        t.omega = nullptr;
+        t.ldo = 0;
+        t.Y = rq.Y;
+        t.ldy = rq.ldy;
+        t.y_f64 = rq.y_f64;
+        t.beta = rq.beta;
+        t.partials = rq.partials;
+        t.strip = strip;
+        t.single = (rq.strips == 1);
+        if (!first) lds_barrier_m();
+        first = false;
+        lp_tile<NT, ADT, kLpBatchWaves, true>(t, oh, ol);
+    }
+}
+
+template <int NT, int ADT, int W, bool GEN>
+hipError_t launch_lp(const MArgs& a, dim3 grid, hipStream_t s) {
+    grid.y = (unsigned)((a.m + 64 * W - 1) / (64 * W));
+    hipLaunchKernelGGL((k_gemm_mfma_lp<NT, ADT, W, GEN>), grid, dim3(64 * W), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int NT, int ADT, bool GEN>
+hipError_t dispatch_lp_w(int waves, const MArgs& a, dim3 grid, hipStream_t s) {
+    switch (waves) {
+    case 4: return launch_lp<NT, ADT, 4, GEN>(a, grid, s);
+    case 8: return launch_lp<NT, ADT, 8, GEN>(a, grid, s);
+    default: return launch_lp<NT, ADT, 16, GEN>(a, grid, s);
+    }
+}
+
+template <int ADT, bool GEN>
+hipError_t dispatch_lp(int nt, int waves, const MArgs& a, dim3 grid, hipStream_t s) {
+    switch (nt) {
+    case 1: return dispatch_lp_w<1, ADT, GEN>(waves, a, grid, s);
+    case 2: return dispatch_lp_w<2, ADT, GEN>(waves, a, grid, s);
+    default: return dispatch_lp_w<4, ADT, GEN>(waves, a, grid, s);
+    }
+}
+
 template <int NT, bool GEN>
 hipError_t launch_m(const MArgs& a, dim3 grid, hipStream_t s) {
     hipLaunchKernelGGL((k_gemm_mfma<NT, GEN>), grid, dim3(kThreads), 0, s, a);
@@ -432,6 +754,95 @@ hipError_t launch_gemm_mfma_batch(const BatchArgs& a, int nt, int grid, hipStrea
     case 4: e = run_mfma_batch<4>(a, grid, s); break;
     case 8: e = run_mfma_batch<8>(a, grid, s); break;
     default: return hipErrorInvalidValue;
+    }
+    if (e != hipSuccess) return e;
+    return launch_reduce_batch(a, s);
+}
+
+int lp_ntiles(int64_t k) { return k <= 16 ? 1 : k <= 32 ? 2 : 4; }
+
+// Waves per workgroup of the low-precision kernel.  With one N-tile the Omega
+// chunk is small and 4-wave workgroups win (several per compute unit, whose
+// chunk phases do not line up: measured 3.2 vs 2.6 TB/s for FP8 at k = 5);
+// with more N-tiles generation dominates and 8 waves share each chunk (k = 64:
+// 1.7 vs 1.2 TB/s for FP8), unless that leaves compute units without a tile.
+int lp_waves(int64_t m, int64_t strips, int64_t nblk, int nt) {
+    if (nt == 1) return 4;
+    const int64_t tiles8 = strips * ((m + 511) / 512) * nblk;
+    return tiles8 >= device_cus() ? 8 : 4;
+}
+
+hipError_t launch_gemm_mfma_lp(const GemmLaunch& g) {
+    const int nt = lp_ntiles(g.k);
+    const int64_t BN = 16 * nt;
+    const int64_t nblk = (g.k + BN - 1) / BN;
+    int64_t S = 0;
+    for (int b = 0; b < g.P; ++b) S += (g.blk[b].n + kLpStrip - 1) / kLpStrip;
+    MArgs a{};
+    a.m = g.m;
+    a.k = g.k;
+    a.ldy = g.ldy;
+    a.ldo = g.ldo;
+    a.omega = g.omega;
+    a.Y = g.Y;
+    a.partials = S > 1 ? static_cast<float*>(g.workspace) : nullptr;
+    a.key0 = (uint32_t)g.seed;
+    a.key1 = (uint32_t)(g.seed >> 32);
+    a.col0 = g.col0;
+    a.P = g.P;
+    a.S_total = (int)S;
+    a.y_f64 = g.y_f64;
+    a.beta = g.beta;
+    for (int b = 0; b < g.P; ++b) a.blk[b] = g.blk[b];
+    const int waves = lp_waves(g.m, S, nblk, nt);
+    const dim3 grid((unsigned)S, 1u, (unsigned)nblk);
+    const TraceEvents& tr = g.trace;
+    if (tr.begin) (void)hipEventRecord(tr.begin, g.stream);
+    const bool gen = (g.omega == nullptr);
+    hipError_t e;
+    if (g.adtype == 1)
+        e = gen ? dispatch_lp<1, true>(nt, waves, a, grid, g.stream)
+                : dispatch_lp<1, false>(nt, waves, a, grid, g.stream);
+    else
+        e = gen ? dispatch_lp<2, true>(nt, waves, a, grid, g.stream)
+                : dispatch_lp<2, false>(nt, waves, a, grid, g.stream);
+    if (e != hipSuccess) return e;
+    if (tr.mid) (void)hipEventRecord(tr.mid, g.stream);
+    if (S > 1) e = launch_reduce_partials(a.partials, (int)S, g.m, g.k, g.Y, g.y_f64, g.ldy,
+                                          g.beta, g.stream);
+    if (tr.end) (void)hipEventRecord(tr.end, g.stream);
+    return e;
+}
+
+namespace {
+
+template <int NT, int ADT>
+hipError_t run_lp_batch(const BatchArgs& a, int grid, hipStream_t s) {
+    static const int per_cu = [] {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gemm_mfma_lp_batch<NT, ADT>,
+                                                         64 * kLpBatchWaves, 0) != hipSuccess)
+            n = 1;
+        return n;
+    }();
+    grid = batch_grid(per_cu, a.total_tiles, grid);
+    hipLaunchKernelGGL((k_gemm_mfma_lp_batch<NT, ADT>), dim3((unsigned)grid),
+                       dim3(64 * kLpBatchWaves), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_gemm_mfma_lp_batch(const BatchArgs& a, int nt, int adtype, int grid,
+                                     hipStream_t s) {
+    if (a.count == 0 || a.total_tiles == 0) return hipSuccess;
+    hipError_t e;
+    if (adtype == 1) {
+        e = nt == 1 ? run_lp_batch<1, 1>(a, grid, s) : nt == 2 ? run_lp_batch<2, 1>(a, grid, s)
+                                                              : run_lp_batch<4, 1>(a, grid, s);
+    } else {
+        e = nt == 1 ? run_lp_batch<1, 2>(a, grid, s) : nt == 2 ? run_lp_batch<2, 2>(a, grid, s)
+                                                              : run_lp_batch<4, 2>(a, grid, s);
     }
     if (e != hipSuccess) return e;
     return launch_reduce_batch(a, s);

@@ -36,11 +36,13 @@ size_t up256(size_t b) { return (b + 255) / 256 * 256; }
 // Tiles, strips and memory of one request: exactly what a direct call on the
 // same arguments would use.
 struct Geometry {
-    bool mfma = false;
+    enum Path { kStream = 0, kMfma = 1, kMfmaLp = 2 };
+    int path = kStream;
     int kclass = 0;          // streaming kernel: sketch-width class
-    int nt = 0;              // matrix-core kernel: N-tiles of 16 columns
+    int nt = 0;              // matrix-core kernels: N-tiles of 16 columns
     int64_t strips = 0;      // contraction strips (partials when > 1)
-    int64_t ncols = 0;       // column groups (streaming) or column blocks (matrix core)
+    int64_t ncols = 0;       // column groups (streaming) or column blocks (matrix cores)
+    int64_t rows = 0;        // rows per matrix-core tile
     size_t partial_bytes = 0;
     int64_t a_ld = 0;        // ld of a staged A (elements)
     size_t a_bytes = 0;      // staged A bytes (0 for device A)
@@ -50,13 +52,20 @@ struct Geometry {
 
 Geometry geometry(const sk_request& r) {
     Geometry g;
-    g.mfma = sk::use_mfma(r.a_dtype, r.k);
     const int64_t C = sk::strip_width_for(r.a_dtype, r.k);
     g.strips = (r.n + C - 1) / C;
-    if (g.mfma) {
+    if (sk::use_mfma(r.a_dtype, r.k)) {
+        g.path = Geometry::kMfma;
         g.nt = sk::mfma_ntiles(r.k);
+        g.rows = sk::kMfmaRows;
         g.ncols = (r.k + 16 * g.nt - 1) / (16 * g.nt);
         g.tile_class = 1000 + g.nt;
+    } else if (sk::use_mfma_lp(r.a_dtype, r.k)) {
+        g.path = Geometry::kMfmaLp;
+        g.nt = sk::lp_ntiles(r.k);
+        g.rows = sk::kLpBatchRows;
+        g.ncols = (r.k + 16 * g.nt - 1) / (16 * g.nt);
+        g.tile_class = 2000 + 10 * r.a_dtype + g.nt;
     } else {
         g.kclass = sk::k_class((int)std::min<int64_t>(r.k, sk::kColGroup));
         g.ncols = (r.k + sk::kColGroup - 1) / sk::kColGroup;
@@ -200,8 +209,9 @@ void launch_batch(sk_server* S, const sk::Batch& b, const std::vector<ServerReq*
         x.y_f64 = r.y_dtype == SK_Y_F64;
         x.beta = r.beta;
         x.strips = (int32_t)q.g.strips;
-        x.rows_per_wg = (int32_t)(q.g.mfma ? sk::kMfmaRows
-                                           : sk::rows_per_tile(r.m, q.g.strips, q.g.ncols));
+        x.rows_per_wg = (int32_t)(q.g.path != Geometry::kStream
+                                      ? q.g.rows
+                                      : sk::rows_per_tile(r.m, q.g.strips, q.g.ncols));
         x.rowblocks = (int32_t)((r.m + x.rows_per_wg - 1) / x.rows_per_wg);
         x.tile_begin = tiles;
         x.out_begin = outs;
@@ -211,9 +221,15 @@ void launch_batch(sk_server* S, const sk::Batch& b, const std::vector<ServerReq*
     a.total_tiles = tiles;
     a.total_outputs = outs;
     const ServerReq& q0 = *rq[0];
-    if (err == hipSuccess)
-        err = q0.g.mfma ? sk::launch_gemm_mfma_batch(a, q0.g.nt, 0, st)
-                        : sk::launch_gemm_batch(a, q0.g.kclass, q0.r.a_dtype, 0, st);
+    if (err == hipSuccess) {
+        switch (q0.g.path) {
+        case Geometry::kMfma: err = sk::launch_gemm_mfma_batch(a, q0.g.nt, 0, st); break;
+        case Geometry::kMfmaLp:
+            err = sk::launch_gemm_mfma_lp_batch(a, q0.g.nt, q0.r.a_dtype, 0, st);
+            break;
+        default: err = sk::launch_gemm_batch(a, q0.g.kclass, q0.r.a_dtype, 0, st);
+        }
+    }
     if (err == hipSuccess) err = hipEventRecord(f.ev[2], st);
     if (err != hipSuccess) {
         f.status = SK_EHIP;

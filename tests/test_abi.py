@@ -150,7 +150,9 @@ def test_workspace_size_rules():
     assert ws(0, F32, 4096, 32768, 17, 1) == 16 * 4096 * 17 * 4
     assert sk.sketch_strip_width(F32, 5) == 1024 and sk.sketch_strip_width(F32, 9) == 512
     assert sk.sketch_strip_width(F32, 17) == 2048
+    # FP8 at every k and BF16 past 16 columns: BF16 matrix cores, 4096-column strips
     assert sk.sketch_strip_width(BF16, 5) == 2048 and sk.sketch_strip_width(FP8, 4) == 4096
+    assert sk.sketch_strip_width(BF16, 17) == 4096 and sk.sketch_strip_width(FP8, 256) == 4096
 
 
 def test_python_binding_requires_library(monkeypatch, tmp_path):

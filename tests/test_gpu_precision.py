@@ -3,7 +3,11 @@ power-of-two scales), products accumulated in FP32, strips summed in FP64.
 
 * quantised codes and scales: bit-exact against the oracle's codecs;
 * Y against the oracle on the dequantised A: within the FP32 summation bound
-  (the quantisation is exact input data, so this isolates the arithmetic);
+  (the quantisation is exact input data, so this isolates the arithmetic).  On
+  the VALU path (BF16, k <= 16) chains are <= 16 products per lane plus lane
+  levels (bound 80u); on the BF16 matrix-core path (FP8 at every k, BF16 for
+  k > 16) a chain runs over a 4096-column strip and Omega enters as hi + lo BF16
+  terms whose sum is within 2^-16 = 256u of Omega (bound (4096 + 4 + 256)u);
 * Y against the oracle on the original FP32 A (end-to-end error): relative
   Frobenius <= 1e-2 for BF16 (the stated target); for FP8 the error is reported
   and held to the model's order (3 mantissa bits: <= 5e-2).
@@ -57,14 +61,22 @@ def test_fp8_zero_block_scale_is_one():
     assert not Aq.cpu().numpy()[128:].any()
 
 
-def _deq_bound(Adeq, Y, seed, row0, k, ref):
-    Om = oracle.omega_block(seed, row0, Adeq.shape[1], 0, k)
+def chain(kind, k):
+    """FP32 summation-bound constant of the kernel that serves (storage, k)."""
+    on_matrix_cores = kind == "fp8" or (kind == "bf16" and k > 16)
+    return 4096 + 4 + 256 if on_matrix_cores else 80
+
+
+def _deq_bound(Adeq, Y, seed, row0, k, ref, kind, col0=0):
+    Om = oracle.omega_block(seed, row0, Adeq.shape[1], col0, k)
     mag = oracle.matmul(np.abs(Adeq).astype(np.float32), np.abs(Om))
     err = np.abs(Y - ref)
-    assert (err <= 80 * U * mag + U * np.abs(ref)).all(), float((err - 80 * U * mag).max())
+    c = chain(kind, k)
+    assert (err <= c * U * mag + U * np.abs(ref)).all(), float((err - c * U * mag).max())
 
 
-@pytest.mark.parametrize("m,n,k,row0", [(300, 5000, 5, 0), (200, 3000, 16, 7), (130, 2100, 40, 4)])
+@pytest.mark.parametrize("m,n,k,row0", [(300, 5000, 5, 0), (200, 3000, 16, 7), (130, 2100, 40, 4),
+                                        (600, 9000, 64, 1), (257, 4097, 17, 0), (90, 5000, 130, 2)])
 def test_bf16_product(m, n, k, row0):
     A = normal_matrix(m, n, seed=3 * m + k)
     Aq, _ = sk.sketch_quantize(dev_f32(A), "bf16")
@@ -72,13 +84,14 @@ def test_bf16_product(m, n, k, row0):
     codes = Aq.cpu().view(torch.int16).numpy().view(np.uint16)
     ref_q = oracle.gen_matmul_q(codes, "bf16", None, 11, row0, 0, k)
     Adeq = oracle.bf16_decode(codes)
-    _deq_bound(Adeq, Y, 11, row0, k, ref_q)
+    _deq_bound(Adeq, Y, 11, row0, k, ref_q, "bf16")
     e2e = oracle.rel_fro(Y, oracle.gen_matmul(A, 11, row0, 0, k))
     assert e2e <= 1e-2, e2e
     assert e2e >= 1e-4          # BF16 storage does lose precision: the test sees it
 
 
-@pytest.mark.parametrize("m,n,k,row0", [(300, 5000, 5, 0), (260, 3000, 16, 9)])
+@pytest.mark.parametrize("m,n,k,row0", [(300, 5000, 5, 0), (260, 3000, 16, 9), (600, 9000, 64, 3),
+                                        (70, 4100, 100, 0), (1100, 800, 1, 5)])
 def test_fp8_product(m, n, k, row0):
     A = normal_matrix(m, n, seed=5 * m + k)
     A[128:256] *= np.float32(0.01)
@@ -88,7 +101,7 @@ def test_fp8_product(m, n, k, row0):
     s = sc.cpu().numpy()
     ref_q = oracle.gen_matmul_q(Q, "fp8", s, 12, row0, 0, k)
     Adeq = oracle.fp8_decode_table()[Q] * np.repeat(s.astype(np.float64), 128)[:m, None]
-    _deq_bound(Adeq, Y, 12, row0, k, ref_q)
+    _deq_bound(Adeq, Y, 12, row0, k, ref_q, "fp8")
     e2e = oracle.rel_fro(Y, oracle.gen_matmul(A, 12, row0, 0, k))
     assert e2e <= 5e-2, e2e
 
@@ -136,3 +149,28 @@ def test_full_size_errors_sampled_rows():
           {f"{a}/k={k}": f"{e:.3e}" for (a, k), e in report.items()})
     del A
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("kind,k", [("bf16", 64), ("fp8", 5), ("fp8", 64)])
+def test_matrix_core_layouts_and_stored_omega_bitwise(kind, k):
+    """BF16 matrix-core path: 1Dred over whole 4096-column strips equals the row
+    layout bitwise, row blocks equal rows of the whole, and the stored-Omega
+    product equals the generated one bitwise."""
+    m, P = 700, 3
+    w = sk.sketch_strip_width(1 if kind == "bf16" else 2, k)
+    assert w == 4096
+    n = P * w
+    A = normal_matrix(m, n, seed=91)
+    Aq, sc = sk.sketch_quantize(dev_f32(A), kind)
+    Yrow = sk.sketch_gen_matmul(Aq, 6, k, a_scales=sc)
+    Yred = sk.sketch_gen_matmul_reduce([Aq[:, b * w:(b + 1) * w] for b in range(P)],
+                                       [b * w for b in range(P)], 6, k,
+                                       scales=None if sc is None else [sc] * P)
+    assert torch.equal(Yrow, Yred)
+    parts = []
+    for r in range(0, m, 256):      # row blocks on 128-row boundaries keep the FP8 scales aligned
+        parts.append(sk.sketch_gen_matmul(Aq[r:r + 256], 6, k,
+                                          a_scales=None if sc is None else sc[r // 128:]))
+    assert torch.equal(torch.cat(parts), Yrow)
+    Om = sk.sketch_gen_omega(6, 0, n, 0, k, device=DEV)
+    assert torch.equal(sk.sketch_matmul_omega(Aq, Om, a_scales=sc), Yrow)

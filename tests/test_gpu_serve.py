@@ -183,6 +183,26 @@ def test_cancel_queued_request():
     assert st["cancelled"] == 1 and st["completed"] == 2 and st["max_running"] == 1
 
 
+def test_low_precision_requests_bitwise():
+    """BF16 and FP8 requests (matrix-core and VALU classes) served in one mix equal
+    direct calls bitwise."""
+    cases = [("bf16", 700, 9000, 64), ("bf16", 300, 5000, 5), ("fp8", 600, 9000, 5),
+             ("fp8", 257, 4100, 64), ("bf16", 129, 3000, 20)]
+    reqs = []
+    for i, (kind, m, n, k) in enumerate(cases):
+        Aq, sc = sk.sketch_quantize(dev_matrix(m, n, seed=60 + i)[1], kind)
+        reqs.append((Aq, sc, k, sk.sketch_gen_matmul(Aq, 70 + i, k, a_scales=sc)))
+    Ys = [torch.empty((A.shape[0], k), device=DEV) for A, _, k, _ in reqs]
+    torch.cuda.synchronize()
+    with sk.SketchServer(1 << 30, max_slots=8, max_batch=8) as srv:
+        ts = [srv.submit(sv.make_request(A=A, k=k, seed=70 + i, Y=Y, a_scales=sc), A, sc, Y)
+              for i, ((A, sc, k, _), Y) in enumerate(zip(reqs, Ys))]
+        infos = [srv.wait(t, 60.0) for t in ts]
+    assert all(x["state"] == sv.SK_REQ_DONE for x in infos)
+    for (A, sc, k, Yd), Y in zip(reqs, Ys):
+        assert torch.equal(Y, Yd), (A.dtype, A.shape, k)
+
+
 def test_request_validation():
     Y = torch.empty((10, 5), device=DEV)
     A = torch.empty((10, 64), device=DEV)
