@@ -50,6 +50,13 @@ def _load():
     lib.oracle_spec_cossin_batch.argtypes = [P, P, P, i64]
     lib.oracle_omega_value.argtypes = [u64, i64, i64]
     lib.oracle_omega_value.restype = ctypes.c_float
+    lib.oracle_omega_value_dist.argtypes = [u64, i64, i64, ctypes.c_int]
+    lib.oracle_omega_value_dist.restype = ctypes.c_float
+    lib.oracle_omega_block_dist.argtypes = [u64, i64, i64, i64, i64, ctypes.c_int, P]
+    lib.oracle_gen_matmul_dist_f64.argtypes = [P, i64, i64, i64, u64, i64, i64, i64,
+                                               ctypes.c_int, P]
+    lib.oracle_gen_matmul_reduce_dist_f64.argtypes = [P, i64, i64, P, P, P, u64, i64, i64,
+                                                      ctypes.c_int, P]
     lib.oracle_omega_f64ref.argtypes = [u64, i64, i64]
     lib.oracle_omega_f64ref.restype = ctypes.c_double
     lib.oracle_omega_block.argtypes = [u64, i64, i64, i64, i64, P]
@@ -125,33 +132,43 @@ def spec_cossin(mo: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
     return c, s
 
 
-def omega_value(seed: int, row: int, col: int) -> float:
-    return float(_load().oracle_omega_value(seed, row, col))
+DISTS = {"normal": 0, "uniform": 1, "rademacher": 2}
+
+
+def _dist(dist) -> int:
+    return DISTS[dist] if isinstance(dist, str) else int(dist)
+
+
+def omega_value(seed: int, row: int, col: int, dist="normal") -> float:
+    """Omega(row, col) under the given distribution ("normal", "uniform", "rademacher")."""
+    return float(_load().oracle_omega_value_dist(seed, row, col, _dist(dist)))
 
 
 def omega_f64ref(seed: int, row: int, col: int) -> float:
     return float(_load().oracle_omega_f64ref(seed, row, col))
 
 
-def omega_block(seed: int, row0: int, n: int, col0: int, k: int) -> np.ndarray:
+def omega_block(seed: int, row0: int, n: int, col0: int, k: int, dist="normal") -> np.ndarray:
     """Omega[row0:row0+n, col0:col0+k] (FP32, n x k)."""
     out = np.empty((n, k), dtype=np.float32)
     if n and k:
-        _load().oracle_omega_block(seed, row0, n, col0, k, _ptr(out))
+        _load().oracle_omega_block_dist(seed, row0, n, col0, k, _dist(dist), _ptr(out))
     return out
 
 
-def gen_matmul(A: np.ndarray, seed: int, row0: int, col0: int, k: int) -> np.ndarray:
+def gen_matmul(A: np.ndarray, seed: int, row0: int, col0: int, k: int,
+               dist="normal") -> np.ndarray:
     """Y = A * Omega(seed)[row0:row0+n, col0:col0+k] in FP64 (A is FP32 m x n)."""
     A, lda = _rows(A, np.float32)
     m, n = A.shape
     Y = np.zeros((m, k), dtype=np.float64)
     if m and k:
-        _load().oracle_gen_matmul_f64(_ptr(A), m, n, lda, seed, row0, col0, k, _ptr(Y))
+        _load().oracle_gen_matmul_dist_f64(_ptr(A), m, n, lda, seed, row0, col0, k, _dist(dist),
+                                           _ptr(Y))
     return Y
 
 
-def gen_matmul_reduce(blocks, row0s, seed: int, col0: int, k: int) -> np.ndarray:
+def gen_matmul_reduce(blocks, row0s, seed: int, col0: int, k: int, dist="normal") -> np.ndarray:
     """Y = sum_b A_b * Omega[row0_b : row0_b + n_b, col0:col0+k], blocks in order (FP64)."""
     views = [_rows(b, np.float32) for b in blocks]
     m = views[0][0].shape[0]
@@ -165,8 +182,8 @@ def gen_matmul_reduce(blocks, row0s, seed: int, col0: int, k: int) -> np.ndarray
     r0 = np.array(row0s, dtype=np.int64)
     Y = np.zeros((m, k), dtype=np.float64)
     if m and k:
-        _load().oracle_gen_matmul_reduce_f64(ptrs, P, m, _ptr(n_b), _ptr(lda_b), _ptr(r0), seed,
-                                             col0, k, _ptr(Y))
+        _load().oracle_gen_matmul_reduce_dist_f64(ptrs, P, m, _ptr(n_b), _ptr(lda_b), _ptr(r0),
+                                                  seed, col0, k, _dist(dist), _ptr(Y))
     return Y
 
 

@@ -20,6 +20,9 @@
  *    from the even word and the angle 2*pi*u from the odd word;
  *  - the FP32 value of each normal is fixed by the operation sequence in
  *    oracle_normal_pair() below (fma-only series, correctly rounded div/sqrt).
+ *  - other distributions of Omega (the paper's experiments draw uniform
+ *    entries, Sec. 6.3): "uniform" is the u of the entry's own word, in (0, 1);
+ *    "Rademacher" is +1 when the word's top bit is 0, else -1.
  *
  * Build: gcc -O2 -std=c11 -fopenmp -ffp-contract=off -fPIC -shared.
  */
@@ -186,15 +189,22 @@ void oracle_normal_pair(uint32_t r_even, uint32_t r_odd, float* z_cos, float* z_
     *z_sin = rho * s;
 }
 
-float oracle_omega_value(uint64_t seed, int64_t row, int64_t col)
+float oracle_omega_value_dist(uint64_t seed, int64_t row, int64_t col, int dist)
 {
     uint32_t r[4];
     omega_words(seed, row, col, r);
     int t = (int)(row & 3);
+    if (dist == ORACLE_DIST_UNIFORM) return (float)ldexp((double)odd24(r[t]), -24);
+    if (dist == ORACLE_DIST_RADEMACHER) return (r[t] >> 31) ? -1.0f : 1.0f;
     float z[4];
     oracle_normal_pair(r[0], r[1], &z[0], &z[1]);
     oracle_normal_pair(r[2], r[3], &z[2], &z[3]);
     return z[t];
+}
+
+float oracle_omega_value(uint64_t seed, int64_t row, int64_t col)
+{
+    return oracle_omega_value_dist(seed, row, col, ORACLE_DIST_NORMAL);
 }
 
 double oracle_omega_f64ref(uint64_t seed, int64_t row, int64_t col)
@@ -210,13 +220,19 @@ double oracle_omega_f64ref(uint64_t seed, int64_t row, int64_t col)
     return (t & 1) ? rho * sin(th) : rho * cos(th);
 }
 
-void oracle_omega_block(uint64_t seed, int64_t row0, int64_t n, int64_t col0, int64_t k,
-                        float* out)
+void oracle_omega_block_dist(uint64_t seed, int64_t row0, int64_t n, int64_t col0, int64_t k,
+                             int dist, float* out)
 {
 #pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < n; ++j)
         for (int64_t c = 0; c < k; ++c)
-            out[j * k + c] = oracle_omega_value(seed, row0 + j, col0 + c);
+            out[j * k + c] = oracle_omega_value_dist(seed, row0 + j, col0 + c, dist);
+}
+
+void oracle_omega_block(uint64_t seed, int64_t row0, int64_t n, int64_t col0, int64_t k,
+                        float* out)
+{
+    oracle_omega_block_dist(seed, row0, n, col0, k, ORACLE_DIST_NORMAL, out);
 }
 
 /* ------------------------------------------------------------------ */
@@ -236,15 +252,39 @@ void oracle_matmul_f64(const float* A, int64_t m, int64_t n, int64_t lda, const 
     }
 }
 
-void oracle_gen_matmul_f64(const float* A, int64_t m, int64_t n, int64_t lda, uint64_t seed,
-                           int64_t row0, int64_t col0, int64_t k, double* Y)
+void oracle_gen_matmul_dist_f64(const float* A, int64_t m, int64_t n, int64_t lda,
+                                uint64_t seed, int64_t row0, int64_t col0, int64_t k, int dist,
+                                double* Y)
 {
     if (m <= 0 || k <= 0) return;
     if (n <= 0) { memset(Y, 0, sizeof(double) * (size_t)(m * k)); return; }
     float* Om = (float*)malloc(sizeof(float) * (size_t)(n * k));
-    oracle_omega_block(seed, row0, n, col0, k, Om);
+    oracle_omega_block_dist(seed, row0, n, col0, k, dist, Om);
     oracle_matmul_f64(A, m, n, lda, Om, k, k, Y);
     free(Om);
+}
+
+void oracle_gen_matmul_f64(const float* A, int64_t m, int64_t n, int64_t lda, uint64_t seed,
+                           int64_t row0, int64_t col0, int64_t k, double* Y)
+{
+    oracle_gen_matmul_dist_f64(A, m, n, lda, seed, row0, col0, k, ORACLE_DIST_NORMAL, Y);
+}
+
+void oracle_gen_matmul_reduce_dist_f64(const float* const* A_b, int64_t P, int64_t m,
+                                       const int64_t* n_b, const int64_t* lda_b,
+                                       const int64_t* row0_b, uint64_t seed, int64_t col0,
+                                       int64_t k, int dist, double* Y)
+{
+    if (m <= 0 || k <= 0) return;
+    memset(Y, 0, sizeof(double) * (size_t)(m * k));
+    double* part = (double*)malloc(sizeof(double) * (size_t)(m * k));
+    for (int64_t b = 0; b < P; ++b) {
+        oracle_gen_matmul_dist_f64(A_b[b], m, n_b[b], lda_b[b], seed, row0_b[b], col0, k, dist,
+                                   part);
+        if (n_b[b] <= 0) continue;
+        for (int64_t i = 0; i < m * k; ++i) Y[i] += part[i];
+    }
+    free(part);
 }
 
 void oracle_gen_matmul_reduce_f64(const float* const* A_b, int64_t P, int64_t m,
@@ -252,15 +292,8 @@ void oracle_gen_matmul_reduce_f64(const float* const* A_b, int64_t P, int64_t m,
                                   const int64_t* row0_b, uint64_t seed, int64_t col0,
                                   int64_t k, double* Y)
 {
-    if (m <= 0 || k <= 0) return;
-    memset(Y, 0, sizeof(double) * (size_t)(m * k));
-    double* part = (double*)malloc(sizeof(double) * (size_t)(m * k));
-    for (int64_t b = 0; b < P; ++b) {
-        oracle_gen_matmul_f64(A_b[b], m, n_b[b], lda_b[b], seed, row0_b[b], col0, k, part);
-        if (n_b[b] <= 0) continue;
-        for (int64_t i = 0; i < m * k; ++i) Y[i] += part[i];
-    }
-    free(part);
+    oracle_gen_matmul_reduce_dist_f64(A_b, P, m, n_b, lda_b, row0_b, seed, col0, k,
+                                      ORACLE_DIST_NORMAL, Y);
 }
 
 /* ------------------------------------------------------------------ */

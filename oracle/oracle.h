@@ -29,10 +29,17 @@ void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t
 /* Batched form: out[4i..4i+3] = Philox4x32-10(ctr[4i..4i+3], key), i < N. */
 void oracle_philox_raw(const uint32_t* ctr, const uint32_t key[2], uint32_t* out, int64_t N);
 
+/* Distribution of Omega's entries. */
+enum { ORACLE_DIST_NORMAL = 0, ORACLE_DIST_UNIFORM = 1, ORACLE_DIST_RADEMACHER = 2 };
+
 /* Omega entry (global row j, global column c) as the FP32 value the method
  * defines: Box-Muller over the Philox uniforms, evaluated with the fixed FP32
  * operation sequence documented in oracle.c. */
 float oracle_omega_value(uint64_t seed, int64_t row, int64_t col);
+/* The entry under another distribution: ORACLE_DIST_UNIFORM gives the uniform
+ * u = (2 (r >> 9) + 1) 2^-24 of the entry's own Philox word r, in (0, 1);
+ * ORACLE_DIST_RADEMACHER gives +1 if r < 2^31, else -1. */
+float oracle_omega_value_dist(uint64_t seed, int64_t row, int64_t col, int dist);
 /* The FP32 Box-Muller step alone: from the Philox words (r_even, r_odd) to
  * (rho cos theta, rho sin theta) with u = (2 (r >> 9) + 1) 2^-24,
  * rho = sqrt(-2 ln u_even), theta = 2 pi u_odd. */
@@ -47,11 +54,16 @@ double oracle_omega_f64ref(uint64_t seed, int64_t row, int64_t col);
 /* Omega[row0:row0+n, col0:col0+k] as an n x k row-major FP32 block. */
 void oracle_omega_block(uint64_t seed, int64_t row0, int64_t n, int64_t col0, int64_t k,
                         float* out);
+void oracle_omega_block_dist(uint64_t seed, int64_t row0, int64_t n, int64_t col0, int64_t k,
+                             int dist, float* out);
 
 /* Y (m x k, row-major, FP64) = A (m x n, row-major, leading dim lda, FP32)
  *                              * Omega(seed)[row0:row0+n, col0:col0+k]. */
 void oracle_gen_matmul_f64(const float* A, int64_t m, int64_t n, int64_t lda, uint64_t seed,
                            int64_t row0, int64_t col0, int64_t k, double* Y);
+void oracle_gen_matmul_dist_f64(const float* A, int64_t m, int64_t n, int64_t lda,
+                                uint64_t seed, int64_t row0, int64_t col0, int64_t k, int dist,
+                                double* Y);
 
 /* Contraction split with reduction: Y = sum_b A_b * Omega[row0_b : row0_b+n_b, col0:col0+k],
  * blocks summed in order b = 0..P-1 in FP64. */
@@ -59,6 +71,10 @@ void oracle_gen_matmul_reduce_f64(const float* const* A_b, int64_t P, int64_t m,
                                   const int64_t* n_b, const int64_t* lda_b,
                                   const int64_t* row0_b, uint64_t seed, int64_t col0,
                                   int64_t k, double* Y);
+void oracle_gen_matmul_reduce_dist_f64(const float* const* A_b, int64_t P, int64_t m,
+                                       const int64_t* n_b, const int64_t* lda_b,
+                                       const int64_t* row0_b, uint64_t seed, int64_t col0,
+                                       int64_t k, int dist, double* Y);
 
 /* Product with an explicit Omega (n x k row-major FP32, leading dim ldo). */
 void oracle_matmul_f64(const float* A, int64_t m, int64_t n, int64_t lda, const float* Om,

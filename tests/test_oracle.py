@@ -178,6 +178,54 @@ def test_omega_statistics():
     assert abs(np.corrcoef(Z[:, 0], Z2[:, 0])[0, 1]) < 5 / math.sqrt(Z.shape[0])
 
 
+def test_uniform_entries_feed_the_normal_pairs():
+    """Uniform Omega: entry (j, c) is the uniform of its own Philox word, so the
+    uniforms of rows 4q and 4q+1 are exactly the Box-Muller inputs of the normal
+    entries of those rows (checked against FP64 libm Box-Muller on the uniform
+    values), and every value is an odd multiple of 2^-24 in (0, 1)."""
+    seed = 987654321
+    for q, c in ((0, 0), (7, 3), (12345, 1), ((1 << 33) + 5, 999)):
+        u = [oracle.omega_value(seed, 4 * q + t, c, "uniform") for t in range(4)]
+        for pair in (0, 1):
+            ue, uo = u[2 * pair], u[2 * pair + 1]
+            rho = math.sqrt(-2 * math.log(ue))
+            for t, ref in ((0, rho * math.cos(2 * math.pi * uo)), (1, rho * math.sin(2 * math.pi * uo))):
+                z = oracle.omega_value(seed, 4 * q + 2 * pair + t, c)
+                assert abs(z - ref) <= 5 * float(np.spacing(np.float32(abs(ref)))) + 4 * rho * 2.0 ** -24 * 2e-6
+    U = oracle.omega_block(seed, 0, 1 << 16, 0, 3, "uniform").astype(np.float64)
+    m = U * 2.0 ** 24
+    assert np.all(m == np.round(m)) and np.all(np.round(m) % 2 == 1)
+    assert U.min() > 0 and U.max() < 1
+
+
+def test_uniform_and_rademacher_statistics_and_signs():
+    from scipy import stats
+
+    U = oracle.omega_block(3, 0, 1 << 18, 0, 4, "uniform").ravel().astype(np.float64)
+    assert abs(U.mean() - 0.5) < 5 * math.sqrt(1 / 12 / U.size)
+    assert abs(U.var() - 1 / 12) < 5 * math.sqrt((1 / 80 - 1 / 144) / U.size)
+    assert stats.kstest(U, "uniform").pvalue > 1e-4
+    R = oracle.omega_block(3, 0, 1 << 18, 0, 4, "rademacher").ravel()
+    # the sign is the word's top bit, i.e. the uniform of the same entry vs 1/2
+    assert np.array_equal(R, np.where(U < 0.5, 1.0, -1.0).astype(np.float32))
+    assert set(np.unique(R)) == {-1.0, 1.0}
+    assert abs(R.astype(np.float64).mean()) < 5 / math.sqrt(R.size)
+
+
+def test_rademacher_product_of_integer_matrix_is_exact():
+    rng = np.random.default_rng(8)
+    A = rng.integers(-100, 101, size=(37, 900)).astype(np.float32)
+    R = oracle.omega_block(21, 50, 900, 4, 6, "rademacher")
+    ref = A.astype(np.int64) @ R.astype(np.int64)
+    Y = oracle.gen_matmul(A, 21, 50, 4, 6, "rademacher")
+    assert np.array_equal(Y, ref.astype(np.float64))
+    Yu = oracle.gen_matmul(A, 21, 50, 4, 6, "uniform")
+    Uo = oracle.omega_block(21, 50, 900, 4, 6, "uniform").astype(np.float64)
+    assert np.allclose(Yu, A.astype(np.float64) @ Uo, rtol=1e-13, atol=1e-9)
+    Yr = oracle.gen_matmul_reduce([A[:, :400], A[:, 400:]], [50, 450], 21, 4, 6, "rademacher")
+    assert np.array_equal(Yr, Y)
+
+
 def test_omega_block_is_slice_of_global():
     full = oracle.omega_block(9, 0, 300, 0, 40)
     for row0, n, col0, k in [(0, 300, 0, 40), (3, 101, 7, 5), (1, 1, 39, 1), (257, 43, 0, 16)]:
