@@ -59,10 +59,11 @@ def parse():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--workload", default="shares",
-                   choices=["shares", "ksweep", "precision", "serve"],
+                   choices=["shares", "ksweep", "precision", "serve", "dists"],
                    help="shares: the headline step (default); ksweep: 65536x16384, k in "
                         "{5,16,64,256}, generated vs stored Omega; precision: BF16 / FP8 A; "
-                        "serve: Poisson stream of uneven requests through the request server")
+                        "serve: Poisson stream of uneven requests through the request server; "
+                        "dists: normal / uniform / Rademacher Omega on 32768x32768")
     p.add_argument("--serve-requests", type=int, default=2000,
                    help="requests of the served stream (also summarised in the default line)")
     p.add_argument("--serve-slots", type=int, default=32, help="server in-flight slots")
@@ -212,6 +213,37 @@ def run_precision(args):
            "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "higher_is_better": True,
            "dtype": "bf16/fp8 storage, f32 accumulate", "data": "synthetic",
            "config": {"workload": "A 32768x32768 N(0,1), k in {5, 64}"}, "rows": rows}
+    print(json.dumps(out), flush=True)
+
+
+def run_dists(args):
+    """Distribution of Omega (normal, uniform, Rademacher; the paper's experiments draw
+    uniform entries, Sec. 6.3): one call over a 32768 x 32768 FP32 A at k = 5 and 64."""
+    import torch
+
+    import paper_2603_20966_amd as sk
+    from sketch_inputs import normal_matrix_device
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    N = 32768
+    A = normal_matrix_device(N, N, seed=0, device=dev)
+    rows = []
+    for k in (5, 64):
+        Y = torch.empty((N, k), device=dev)
+        for dist in ("normal", "uniform", "rademacher"):
+            t, tmin = _timeit(torch, stream, lambda: sk.sketch_gen_matmul(A, 1, k, Y=Y, dist=dist,
+                                                                          stream=stream),
+                              args.steps)
+            gbps = N * N * 4 / (t * 1e-3) / 1e9
+            rows.append({"dist": dist, "k": k, "ms": round(t, 4), "A_GBps": round(gbps, 1),
+                         "frac_hbm": round(gbps / HBM_PEAK_GBPS, 4),
+                         "TFLOPs": round(2 * N * N * k / (t * 1e-3) / 1e12, 2)})
+    out = {"metric": "A-stream GB/s, Y=A*Omega(seed) by distribution of Omega", "unit": "GB/s",
+           "n_gpus": 1, "steps": args.steps, "higher_is_better": True, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "A 32768x32768 fp32 N(0,1), one call, k in {5, 64}"},
+           "rows": rows}
     print(json.dumps(out), flush=True)
 
 
@@ -366,6 +398,8 @@ def main():
         return run_precision(args)
     if args.workload == "serve":
         return run_serve(args, torch)
+    if args.workload == "dists":
+        return run_dists(args)
 
     import paper_2603_20966_amd as sk
     from sketch_inputs import normal_matrix_device

@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define SKETCH_ABI_VERSION 2
+#define SKETCH_ABI_VERSION 3
 
 enum sk_status {
     SK_OK = 0,
@@ -77,6 +77,14 @@ enum sk_adtype {
 /* Storage type of Y.  The reduction over column strips and blocks is carried
  * out in FP64 and rounded once to the output type. */
 enum sk_ydtype { SK_Y_F32 = 0, SK_Y_F64 = 1 };
+
+/* Distribution of Omega's entries, all from the same Philox word of the entry
+ * (word j mod 4 of counter (j div 4, c, 0) under key seed):
+ *   SK_DIST_NORMAL      Box-Muller N(0,1) (the definition above; the default);
+ *   SK_DIST_UNIFORM     u = (2 (r >> 9) + 1) 2^-24 in (0, 1), exact in FP32 (the
+ *                       paper's experiments draw uniform entries, Sec. 6.3);
+ *   SK_DIST_RADEMACHER  +1 if r < 2^31, else -1. */
+enum sk_dist { SK_DIST_NORMAL = 0, SK_DIST_UNIFORM = 1, SK_DIST_RADEMACHER = 2 };
 
 /* Version of this ABI (SKETCH_ABI_VERSION of the built library). */
 int sketch_abi_version(void);
@@ -127,6 +135,13 @@ int sketch_gen_matmul(const void* A, int a_dtype, int64_t m, int64_t n, int64_t 
                       int64_t omega_col0, int64_t k, void* Y, int y_dtype, int64_t ldy,
                       int beta, void* workspace, size_t workspace_bytes, void* stream);
 
+/* sketch_gen_matmul with Omega drawn from the distribution `dist` (sk_dist;
+ * SK_EINVAL otherwise).  Results obey every rule stated for sketch_gen_matmul. */
+int sketch_gen_matmul_dist(const void* A, int a_dtype, int64_t m, int64_t n, int64_t lda,
+                           const float* a_scales, uint64_t seed, int dist, int64_t omega_row0,
+                           int64_t omega_col0, int64_t k, void* Y, int y_dtype, int64_t ldy,
+                           int beta, void* workspace, size_t workspace_bytes, void* stream);
+
 /*
  * Contraction split with on-device reduction (Alg. 1 on a (1, P, 1) grid: the
  * local products of P column blocks followed by the sum that Reduce-Scatter /
@@ -151,6 +166,14 @@ int sketch_gen_matmul_reduce(const void* const* A_b, int64_t P, int a_dtype, int
                              int64_t k, void* Y, int y_dtype, int64_t ldy, int beta,
                              void* workspace, size_t workspace_bytes, void* stream);
 
+/* sketch_gen_matmul_reduce with Omega drawn from the distribution `dist`. */
+int sketch_gen_matmul_reduce_dist(const void* const* A_b, int64_t P, int a_dtype, int64_t m,
+                                  const int64_t* n_b, const int64_t* lda_b,
+                                  const int64_t* row0_b, const float* const* a_scales_b,
+                                  uint64_t seed, int dist, int64_t omega_col0, int64_t k,
+                                  void* Y, int y_dtype, int64_t ldy, int beta, void* workspace,
+                                  size_t workspace_bytes, void* stream);
+
 /*
  * Per-phase timing (instrumentation; the paper times each phase separately,
  * Sec. 6): arms the NEXT product call made by this host thread
@@ -171,6 +194,9 @@ int sketch_trace_events(void* ev_begin, void* ev_mid, void* ev_end);
  */
 int sketch_gen_omega(uint64_t seed, int64_t row0, int64_t n, int64_t col0, int64_t k,
                      float* Omega, int64_t ldo, void* stream);
+/* sketch_gen_omega with Omega drawn from the distribution `dist`. */
+int sketch_gen_omega_dist(uint64_t seed, int dist, int64_t row0, int64_t n, int64_t col0,
+                          int64_t k, float* Omega, int64_t ldo, void* stream);
 
 /*
  * Y (=|+=) A * Omega for an explicit Omega in device memory (n x k FP32,

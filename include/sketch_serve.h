@@ -90,6 +90,7 @@ typedef struct sk_request {
     int y_dtype;             /* sk_ydtype                                              */
     int64_t ldy;
     int beta;                /* 0: Y = A*Omega; 1: Y += A*Omega                        */
+    int omega_dist;          /* sk_dist of Omega (0 = normal)                          */
 } sk_request;
 
 /* Times are microseconds on the server's host clock (0 = its creation). */

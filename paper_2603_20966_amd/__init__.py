@@ -25,6 +25,7 @@ LIB_PATH = os.path.join(_HERE, "libsketch.so")
 
 SK_A_F32, SK_A_BF16, SK_A_FP8_E4M3 = 0, 1, 2
 SK_Y_F32, SK_Y_F64 = 0, 1
+SK_DIST = {"normal": 0, "uniform": 1, "rademacher": 2}
 STATUS = {0: "SK_OK", -1: "SK_EINVAL", -2: "SK_EDTYPE", -3: "SK_EALIGN", -4: "SK_EWORKSPACE",
           -5: "SK_EHIP", -6: "SK_ENOMEM", -7: "SK_EUNSUPPORTED", -8: "SK_EBUDGET",
           -9: "SK_EQUEUE", -10: "SK_ETIMEOUT"}
@@ -67,12 +68,18 @@ def lib() -> ctypes.CDLL:
         L.sketch_gen_matmul_reduce.argtypes = [P, i64, i32, i64, P, P, P, P, u64, i64, i64, P, i32,
                                                i64, i32, P, sz, P]
         L.sketch_gen_omega.argtypes = [u64, i64, i64, i64, i64, P, i64, P]
+        L.sketch_gen_matmul_dist.argtypes = [P, i32, i64, i64, i64, P, u64, i32, i64, i64, i64,
+                                             P, i32, i64, i32, P, sz, P]
+        L.sketch_gen_matmul_reduce_dist.argtypes = [P, i64, i32, i64, P, P, P, P, u64, i32, i64,
+                                                    i64, P, i32, i64, i32, P, sz, P]
+        L.sketch_gen_omega_dist.argtypes = [u64, i32, i64, i64, i64, i64, P, i64, P]
         L.sketch_matmul_omega.argtypes = [P, i32, i64, i64, i64, P, P, i64, i64, P, i32, i64, i32,
                                           P, sz, P]
         L.sketch_philox_raw.argtypes = [P, u64, P, i64, P]
         L.sketch_quantize.argtypes = [P, i64, i64, i64, i32, P, i64, P, P]
         L.sketch_trace_events.argtypes = [P, P, P]
-        for f in ("sketch_gen_matmul", "sketch_gen_matmul_reduce",
+        for f in ("sketch_gen_matmul", "sketch_gen_matmul_reduce", "sketch_gen_matmul_dist",
+                  "sketch_gen_matmul_reduce_dist", "sketch_gen_omega_dist",
                   "sketch_gen_omega", "sketch_matmul_omega", "sketch_philox_raw",
                   "sketch_quantize", "sketch_trace_events"):
             getattr(L, f).restype = i32
@@ -112,6 +119,13 @@ def _ydtype(dt) -> int:
     if dt == torch.float64:
         return SK_Y_F64
     raise TypeError(f"unsupported Y dtype {dt}")
+
+
+def _dist(dist) -> int:
+    d = SK_DIST.get(dist, dist) if isinstance(dist, str) else int(dist)
+    if not isinstance(d, int):
+        raise ValueError(f"unknown distribution {dist!r}")
+    return d
 
 
 def _ld(t: torch.Tensor, name: str) -> int:
@@ -171,8 +185,10 @@ def _out(Y, m, k, y_dtype, device):
 def sketch_gen_matmul(A: torch.Tensor, seed: int, k: int, *, omega_row0: int = 0,
                       omega_col0: int = 0, Y: torch.Tensor | None = None, beta: int = 0,
                       a_scales: torch.Tensor | None = None, y_dtype=torch.float32,
-                      workspace: torch.Tensor | None = None, stream=None) -> torch.Tensor:
-    """Y (=|+=) A * Omega(seed)[row0:row0+n, col0:col0+k] (one share, Alg. 1 local product)."""
+                      workspace: torch.Tensor | None = None, stream=None,
+                      dist="normal") -> torch.Tensor:
+    """Y (=|+=) A * Omega(seed)[row0:row0+n, col0:col0+k] (one share, Alg. 1 local product);
+    dist: "normal" (default), "uniform" or "rademacher" entries of Omega."""
     m, n = A.shape
     lda = _ld(A, "A") if m > 0 else max(n, 1)
     Y = _out(Y, m, k, y_dtype if Y is None else Y.dtype, A.device)
@@ -184,16 +200,17 @@ def sketch_gen_matmul(A: torch.Tensor, seed: int, k: int, *, omega_row0: int = 0
         wsp, wsb = _ptr(workspace), workspace.numel() * workspace.element_size()
     else:
         wsp, wsb = workspace_for(need, A.device, st)
-    _check(lib().sketch_gen_matmul(_ptr(A), adt, m, n, lda, _ptr(a_scales), seed, omega_row0,
-                                   omega_col0, k, _ptr(Y), _ydtype(Y.dtype), ldy, beta, wsp, wsb,
-                                   st), "sketch_gen_matmul")
+    _check(lib().sketch_gen_matmul_dist(_ptr(A), adt, m, n, lda, _ptr(a_scales), seed,
+                                        _dist(dist), omega_row0, omega_col0, k, _ptr(Y),
+                                        _ydtype(Y.dtype), ldy, beta, wsp, wsb, st),
+           "sketch_gen_matmul")
     return Y
 
 
 def sketch_gen_matmul_reduce(blocks, row0s, seed: int, k: int, *, omega_col0: int = 0,
                              Y: torch.Tensor | None = None, beta: int = 0, scales=None,
                              y_dtype=torch.float32, workspace: torch.Tensor | None = None,
-                             stream=None) -> torch.Tensor:
+                             stream=None, dist="normal") -> torch.Tensor:
     """Y (=|+=) sum_b A_b * Omega[row0_b:row0_b+n_b, col0:col0+k] (1Dred share, device FP64 sum)."""
     P = len(blocks)
     if P == 0 or len(row0s) != P:
@@ -217,20 +234,21 @@ def sketch_gen_matmul_reduce(blocks, row0s, seed: int, k: int, *, omega_col0: in
         wsp, wsb = _ptr(workspace), workspace.numel() * workspace.element_size()
     else:
         wsp, wsb = workspace_for(need, dev, st)
-    _check(lib().sketch_gen_matmul_reduce(ptrs, P, adt, m, nb, ld, r0, sc, seed, omega_col0, k,
-                                          _ptr(Y), _ydtype(Y.dtype), ldy, beta, wsp, wsb, st),
-           "sketch_gen_matmul_reduce")
+    _check(lib().sketch_gen_matmul_reduce_dist(ptrs, P, adt, m, nb, ld, r0, sc, seed, _dist(dist),
+                                               omega_col0, k, _ptr(Y), _ydtype(Y.dtype), ldy,
+                                               beta, wsp, wsb, st), "sketch_gen_matmul_reduce")
     return Y
 
 
 def sketch_gen_omega(seed: int, row0: int, n: int, col0: int, k: int, *,
-                     out: torch.Tensor | None = None, device="cuda", stream=None) -> torch.Tensor:
+                     out: torch.Tensor | None = None, device="cuda", stream=None,
+                     dist="normal") -> torch.Tensor:
     """Omega(seed)[row0:row0+n, col0:col0+k] materialised (stored-operand alternative)."""
     if out is None:
         out = torch.empty((n, k), dtype=torch.float32, device=device)
     ldo = _ld(out, "Omega") if n > 0 else max(k, 1)
-    _check(lib().sketch_gen_omega(seed, row0, n, col0, k, _ptr(out), ldo,
-                                  _stream(stream, out.device)), "sketch_gen_omega")
+    _check(lib().sketch_gen_omega_dist(seed, _dist(dist), row0, n, col0, k, _ptr(out), ldo,
+                                       _stream(stream, out.device)), "sketch_gen_omega")
     return out
 
 

@@ -97,11 +97,12 @@ int sketch_trace_events(void* ev_begin, void* ev_mid, void* ev_end) {
 }
 
 static int gen_matmul_impl(const void* A, int a_dtype, int64_t m, int64_t n, int64_t lda,
-                           const float* a_scales, uint64_t seed, int64_t omega_row0,
+                           const float* a_scales, uint64_t seed, int dist, int64_t omega_row0,
                            int64_t omega_col0, const float* Omega, int64_t ldo, int64_t k,
                            void* Y, int y_dtype, int64_t ldy, int beta, void* workspace,
                            size_t workspace_bytes, void* stream) {
     const sk::TraceEvents trace = take_trace();
+    if (!dist_ok(dist)) return SK_EINVAL;
     int st = check_common(a_dtype, m, k, omega_col0, Y, y_dtype, ldy, beta);
     if (st != SK_OK) return st;
     st = check_block(A, a_dtype, m, n, lda, omega_row0, a_scales);
@@ -122,6 +123,7 @@ static int gen_matmul_impl(const void* A, int a_dtype, int64_t m, int64_t n, int
     g.k = k;
     g.col0 = (uint32_t)omega_col0;
     g.seed = seed;
+    g.dist = dist;
     g.omega = Omega;
     g.ldo = ldo;
     g.Y = Y;
@@ -139,7 +141,16 @@ int sketch_gen_matmul(const void* A, int a_dtype, int64_t m, int64_t n, int64_t 
                       const float* a_scales, uint64_t seed, int64_t omega_row0,
                       int64_t omega_col0, int64_t k, void* Y, int y_dtype, int64_t ldy,
                       int beta, void* workspace, size_t workspace_bytes, void* stream) {
-    return gen_matmul_impl(A, a_dtype, m, n, lda, a_scales, seed, omega_row0, omega_col0,
+    return gen_matmul_impl(A, a_dtype, m, n, lda, a_scales, seed, SK_DIST_NORMAL, omega_row0,
+                           omega_col0, nullptr, 0, k, Y, y_dtype, ldy, beta, workspace,
+                           workspace_bytes, stream);
+}
+
+int sketch_gen_matmul_dist(const void* A, int a_dtype, int64_t m, int64_t n, int64_t lda,
+                           const float* a_scales, uint64_t seed, int dist, int64_t omega_row0,
+                           int64_t omega_col0, int64_t k, void* Y, int y_dtype, int64_t ldy,
+                           int beta, void* workspace, size_t workspace_bytes, void* stream) {
+    return gen_matmul_impl(A, a_dtype, m, n, lda, a_scales, seed, dist, omega_row0, omega_col0,
                            nullptr, 0, k, Y, y_dtype, ldy, beta, workspace, workspace_bytes,
                            stream);
 }
@@ -149,16 +160,19 @@ int sketch_matmul_omega(const void* A, int a_dtype, int64_t m, int64_t n, int64_
                         void* Y, int y_dtype, int64_t ldy, int beta, void* workspace,
                         size_t workspace_bytes, void* stream) {
     if (n > 0 && m > 0 && k > 0 && (Omega == nullptr || ldo < k)) return SK_EINVAL;
-    return gen_matmul_impl(A, a_dtype, m, n, lda, a_scales, 0, 0, 0, Omega, ldo < 1 ? 1 : ldo, k,
-                           Y, y_dtype, ldy, beta, workspace, workspace_bytes, stream);
+    return gen_matmul_impl(A, a_dtype, m, n, lda, a_scales, 0, SK_DIST_NORMAL, 0, 0, Omega,
+                           ldo < 1 ? 1 : ldo, k, Y, y_dtype, ldy, beta, workspace,
+                           workspace_bytes, stream);
 }
 
-int sketch_gen_matmul_reduce(const void* const* A_b, int64_t P, int a_dtype, int64_t m,
-                             const int64_t* n_b, const int64_t* lda_b, const int64_t* row0_b,
-                             const float* const* a_scales_b, uint64_t seed, int64_t omega_col0,
-                             int64_t k, void* Y, int y_dtype, int64_t ldy, int beta,
-                             void* workspace, size_t workspace_bytes, void* stream) {
+static int gen_matmul_reduce_impl(const void* const* A_b, int64_t P, int a_dtype, int64_t m,
+                                  const int64_t* n_b, const int64_t* lda_b,
+                                  const int64_t* row0_b, const float* const* a_scales_b,
+                                  uint64_t seed, int dist, int64_t omega_col0, int64_t k, void* Y,
+                                  int y_dtype, int64_t ldy, int beta, void* workspace,
+                                  size_t workspace_bytes, void* stream) {
     const sk::TraceEvents trace = take_trace();
+    if (!dist_ok(dist)) return SK_EINVAL;
     int st = check_common(a_dtype, m, k, omega_col0, Y, y_dtype, ldy, beta);
     if (st != SK_OK) return st;
     if (P < 1 || P > sk::kMaxBlocks) return SK_EINVAL;
@@ -182,6 +196,7 @@ int sketch_gen_matmul_reduce(const void* const* A_b, int64_t P, int a_dtype, int
     g.k = k;
     g.col0 = (uint32_t)omega_col0;
     g.seed = seed;
+    g.dist = dist;
     g.omega = nullptr;
     g.Y = Y;
     g.y_f64 = (y_dtype == SK_Y_F64);
@@ -198,15 +213,42 @@ int sketch_gen_matmul_reduce(const void* const* A_b, int64_t P, int a_dtype, int
     return run_product(g, n_total);
 }
 
-int sketch_gen_omega(uint64_t seed, int64_t row0, int64_t n, int64_t col0, int64_t k,
-                     float* Omega, int64_t ldo, void* stream) {
+int sketch_gen_matmul_reduce(const void* const* A_b, int64_t P, int a_dtype, int64_t m,
+                             const int64_t* n_b, const int64_t* lda_b, const int64_t* row0_b,
+                             const float* const* a_scales_b, uint64_t seed, int64_t omega_col0,
+                             int64_t k, void* Y, int y_dtype, int64_t ldy, int beta,
+                             void* workspace, size_t workspace_bytes, void* stream) {
+    return gen_matmul_reduce_impl(A_b, P, a_dtype, m, n_b, lda_b, row0_b, a_scales_b, seed,
+                                  SK_DIST_NORMAL, omega_col0, k, Y, y_dtype, ldy, beta,
+                                  workspace, workspace_bytes, stream);
+}
+
+int sketch_gen_matmul_reduce_dist(const void* const* A_b, int64_t P, int a_dtype, int64_t m,
+                                  const int64_t* n_b, const int64_t* lda_b,
+                                  const int64_t* row0_b, const float* const* a_scales_b,
+                                  uint64_t seed, int dist, int64_t omega_col0, int64_t k,
+                                  void* Y, int y_dtype, int64_t ldy, int beta, void* workspace,
+                                  size_t workspace_bytes, void* stream) {
+    return gen_matmul_reduce_impl(A_b, P, a_dtype, m, n_b, lda_b, row0_b, a_scales_b, seed, dist,
+                                  omega_col0, k, Y, y_dtype, ldy, beta, workspace,
+                                  workspace_bytes, stream);
+}
+
+int sketch_gen_omega_dist(uint64_t seed, int dist, int64_t row0, int64_t n, int64_t col0,
+                          int64_t k, float* Omega, int64_t ldo, void* stream) {
+    if (!dist_ok(dist)) return SK_EINVAL;
     if (n < 0 || k < 0 || row0 < 0 || row0 > kMaxRow - n || col0 < 0 || col0 + k > kMaxCol)
         return SK_EINVAL;
     if (n == 0 || k == 0) return SK_OK;
     if (Omega == nullptr || ldo < k) return SK_EINVAL;
     if (((uintptr_t)Omega & 3u) != 0) return SK_EALIGN;
-    return from_hip(sk::launch_gen_omega(seed, row0, n, col0, k, Omega, ldo,
+    return from_hip(sk::launch_gen_omega(seed, dist, row0, n, col0, k, Omega, ldo,
                                          static_cast<hipStream_t>(stream)));
+}
+
+int sketch_gen_omega(uint64_t seed, int64_t row0, int64_t n, int64_t col0, int64_t k,
+                     float* Omega, int64_t ldo, void* stream) {
+    return sketch_gen_omega_dist(seed, SK_DIST_NORMAL, row0, n, col0, k, Omega, ldo, stream);
 }
 
 int sketch_philox_raw(const uint32_t* ctr, uint64_t seed, uint32_t* out, int64_t N,

@@ -19,6 +19,7 @@ inline int elem_size(int a_dtype) { return a_dtype == SK_A_F32 ? 4 : a_dtype == 
 inline bool adtype_ok(int t) { return t == SK_A_F32 || t == SK_A_BF16 || t == SK_A_FP8_E4M3; }
 inline bool ydtype_ok(int t) { return t == SK_Y_F32 || t == SK_Y_F64; }
 inline bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+inline bool dist_ok(int d) { return d == SK_DIST_NORMAL || d == SK_DIST_UNIFORM || d == SK_DIST_RADEMACHER; }
 
 // Checks of the output side and sizes, shared by every product call.
 inline int check_common(int a_dtype, int64_t m, int64_t k, int64_t col0, const void* Y,

@@ -137,4 +137,19 @@ __device__ __forceinline__ float4 omega4(uint64_t q, uint32_t c, uint32_t k0, ui
     return z;
 }
 
+// Omega entries under another distribution (dist 1: the uniform of each
+// word, exact in FP32; dist 2: Rademacher, +1 when the word's top bit is 0);
+// dist 0 is the normal of omega4.  dist is uniform across a launch.
+__device__ __forceinline__ float4 omega4_dist(uint64_t q, uint32_t c, uint32_t k0, uint32_t k1,
+                                              int dist) {
+    if (dist == 0) return omega4(q, c, k0, k1);
+    Words4 ctr{(uint32_t)q, (uint32_t)(q >> 32), c, 0u};
+    const Words4 r = philox4x32_10(ctr, k0, k1);
+    if (dist == 1)
+        return make_float4((float)odd24(r.x) * 0x1p-24f, (float)odd24(r.y) * 0x1p-24f,
+                           (float)odd24(r.z) * 0x1p-24f, (float)odd24(r.w) * 0x1p-24f);
+    return make_float4((r.x >> 31) ? -1.0f : 1.0f, (r.y >> 31) ? -1.0f : 1.0f,
+                       (r.z >> 31) ? -1.0f : 1.0f, (r.w >> 31) ? -1.0f : 1.0f);
+}
+
 }  // namespace sk

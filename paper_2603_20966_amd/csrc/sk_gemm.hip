@@ -57,6 +57,7 @@ struct KArgs {
     float* partials;
     uint32_t key0, key1;
     uint32_t col0;
+    int dist;
     int P;
     int S_total;
     int rows_per_wg;
@@ -161,6 +162,7 @@ struct Tile {
     int64_t row_begin, row_end;
     int c_base, kg;           // sketch columns [c_base, c_base + kg)
     uint32_t key0, key1, col0;
+    int dist;                 // Omega's distribution (0 normal, 1 uniform, 2 Rademacher)
     const float* omega;       // stored operand (n x k, ldo) when not generated
     int64_t ldo;
     void* Y;
@@ -237,8 +239,8 @@ __device__ __forceinline__ void tile_body(const Tile& tl, float (*om)[strip_widt
         for (int it = tid; it < items; it += kWgThreads) {
             const int qi = it / kg;
             const int c = it - qi * kg;
-            const float4 z = omega4((uint64_t)(q_lo + qi), tl.col0 + (uint32_t)(c_base + c),
-                                    tl.key0, tl.key1);
+            const float4 z = omega4_dist((uint64_t)(q_lo + qi), tl.col0 + (uint32_t)(c_base + c),
+                                         tl.key0, tl.key1, tl.dist);
             const int64_t p0 = 4 * (q_lo + qi) - g0;       // local column of z.x
             if (aligned && p0 + 3 < w) {
                 *reinterpret_cast<float4*>(&om[c][p0]) = z;
@@ -419,6 +421,7 @@ __global__ __launch_bounds__(kWgThreads) void k_gemm_stream(const KArgs args) {
     tl.key0 = args.key0;
     tl.key1 = args.key1;
     tl.col0 = args.col0;
+    tl.dist = args.dist;
     tl.omega = args.omega;
     tl.ldo = args.ldo;
     tl.Y = args.Y;
@@ -466,6 +469,7 @@ __global__ __launch_bounds__(kWgThreads) void k_gemm_batch(const BatchArgs args)
         tl.key0 = (uint32_t)rq.seed;
         tl.key1 = (uint32_t)(rq.seed >> 32);
         tl.col0 = rq.col0;
+        tl.dist = rq.dist;
         tl.omega = nullptr;
         tl.ldo = 0;
         tl.Y = rq.Y;
@@ -642,6 +646,7 @@ hipError_t launch_gemm_stream(const GemmLaunch& g) {
     a.key0 = (uint32_t)g.seed;
     a.key1 = (uint32_t)(g.seed >> 32);
     a.col0 = g.col0;
+    a.dist = g.dist;
     a.P = g.P;
     a.S_total = (int)S;
     a.y_f64 = g.y_f64;

@@ -77,6 +77,7 @@ struct GemmLaunch {
     int64_t k;
     uint32_t col0;
     uint64_t seed;
+    int dist;                 // Omega's distribution: 0 normal, 1 uniform, 2 Rademacher
     const float* omega;       // explicit Omega (n x k) or nullptr to generate
     int64_t ldo;
     void* Y;
@@ -103,6 +104,7 @@ struct BatchReq {
     float* partials;        // [strips][m][k] (unused when strips == 1)
     uint64_t seed;
     uint32_t col0;
+    int32_t dist;
     int32_t y_f64, beta;
     int32_t rows_per_wg, strips, rowblocks;
     int64_t tile_begin, out_begin;
@@ -154,8 +156,8 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_zero_matrix(void* Y, int f64, int64_t m, int64_t k, int64_t ldy, hipStream_t s);
 hipError_t launch_philox_raw(const uint32_t* ctr, uint64_t seed, uint32_t* out, int64_t N,
                              hipStream_t s);
-hipError_t launch_gen_omega(uint64_t seed, int64_t row0, int64_t n, int64_t col0, int64_t k,
-                            float* Om, int64_t ldo, hipStream_t s);
+hipError_t launch_gen_omega(uint64_t seed, int dist, int64_t row0, int64_t n, int64_t col0,
+                            int64_t k, float* Om, int64_t ldo, hipStream_t s);
 hipError_t launch_quantize(const float* A, int64_t m, int64_t n, int64_t lda, int dst, void* Aq,
                            int64_t ldq, float* scales, hipStream_t s);
 

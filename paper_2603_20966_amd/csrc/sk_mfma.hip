@@ -62,6 +62,7 @@ struct MArgs {
     float* partials;
     uint32_t key0, key1;
     uint32_t col0;
+    int dist;
     int P;
     int S_total;
     int y_f64;
@@ -86,6 +87,7 @@ struct MTile {
     int64_t block_row;        // first row of the workgroup (before the wave offset)
     int n_base;
     uint32_t key0, key1, col0;
+    int dist;                 // Omega's distribution (0 normal, 1 uniform, 2 Rademacher)
     const float* omega;
     int64_t ldo;
     void* Y;
@@ -199,8 +201,8 @@ __device__ __forceinline__ void mfma_tile(const MTile& t, float (*om)[16 * NT][l
             for (int it = tid; it < items; it += kThreads) {
                 const int qi = it / kb;
                 const int n = it - qi * kb;
-                const float4 z = omega4((uint64_t)(q_lo + qi), t.col0 + (uint32_t)(n_base + n),
-                                        t.key0, t.key1);
+                const float4 z = omega4_dist((uint64_t)(q_lo + qi), t.col0 + (uint32_t)(n_base + n),
+                                             t.key0, t.key1, t.dist);
                 const int kl0 = (int)(4 * (q_lo + qi) - g0);
                 if (kl0 >= 0 && (kl0 & 3) == 0 && kl0 + 3 < kvalid) {
                     *reinterpret_cast<float4*>(&om[buf][n][kl0]) = z;
@@ -300,6 +302,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm_mfma(const MArgs args) {
     t.key0 = args.key0;
     t.key1 = args.key1;
     t.col0 = args.col0;
+    t.dist = args.dist;
     t.omega = args.omega;
     t.ldo = args.ldo;
     t.Y = args.Y;
@@ -344,6 +347,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm_mfma_batch(const BatchArgs ar
         t.key0 = (uint32_t)rq.seed;
         t.key1 = (uint32_t)(rq.seed >> 32);
         t.col0 = rq.col0;
+        t.dist = rq.dist;
         t.omega = nullptr;
         t.ldo = 0;
         t.Y = rq.Y;
@@ -483,8 +487,8 @@ __device__ __forceinline__ void lp_tile(const MTile& t, uint16_t (*oh)[16 * NT][
             for (int it = tid; it < items; it += TH) {
                 const int qi = it / kb;
                 const int n = it - qi * kb;
-                const float4 z = omega4((uint64_t)(q_lo + qi), t.col0 + (uint32_t)(t.n_base + n),
-                                        t.key0, t.key1);
+                const float4 z = omega4_dist((uint64_t)(q_lo + qi), t.col0 + (uint32_t)(t.n_base + n),
+                                             t.key0, t.key1, t.dist);
                 const int kl0 = (int)(4 * (q_lo + qi) - g0);
                 const float zz[4] = {z.x, z.y, z.z, z.w};
 #pragma unroll
@@ -590,6 +594,7 @@ __global__ __launch_bounds__(64 * W) void k_gemm_mfma_lp(const MArgs args) {
     t.key0 = args.key0;
     t.key1 = args.key1;
     t.col0 = args.col0;
+    t.dist = args.dist;
     t.omega = args.omega;
     t.ldo = args.ldo;
     t.Y = args.Y;
@@ -633,6 +638,7 @@ __global__ __launch_bounds__(64 * kLpBatchWaves) void k_gemm_mfma_lp_batch(const
         t.key0 = (uint32_t)rq.seed;
         t.key1 = (uint32_t)(rq.seed >> 32);
         t.col0 = rq.col0;
+        t.dist = rq.dist;
         t.omega = nullptr;
         t.ldo = 0;
         t.Y = rq.Y;
@@ -710,6 +716,7 @@ hipError_t launch_gemm_mfma(const GemmLaunch& g) {
     a.key0 = (uint32_t)g.seed;
     a.key1 = (uint32_t)(g.seed >> 32);
     a.col0 = g.col0;
+    a.dist = g.dist;
     a.P = g.P;
     a.S_total = (int)S;
     a.y_f64 = g.y_f64;
@@ -789,6 +796,7 @@ hipError_t launch_gemm_mfma_lp(const GemmLaunch& g) {
     a.key0 = (uint32_t)g.seed;
     a.key1 = (uint32_t)(g.seed >> 32);
     a.col0 = g.col0;
+    a.dist = g.dist;
     a.P = g.P;
     a.S_total = (int)S;
     a.y_f64 = g.y_f64;

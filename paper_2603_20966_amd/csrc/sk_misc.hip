@@ -19,14 +19,15 @@ __global__ void k_philox_raw(const uint4* ctr, uint32_t k0, uint32_t k1, uint4* 
 
 // One thread per (Philox counter q, column c): writes Omega rows 4q..4q+3
 // that fall inside [row0, row0+n).
-__global__ void k_gen_omega(uint32_t k0, uint32_t k1, int64_t row0, int64_t n, int64_t col0,
-                            int64_t k, float* Om, int64_t ldo, int64_t q_lo, int64_t nq) {
+__global__ void k_gen_omega(uint32_t k0, uint32_t k1, int dist, int64_t row0, int64_t n,
+                            int64_t col0, int64_t k, float* Om, int64_t ldo, int64_t q_lo,
+                            int64_t nq) {
     const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (it >= nq * k) return;
     const int64_t qi = it / k;
     const int64_t c = it - qi * k;
     const int64_t q = q_lo + qi;
-    const float4 z = omega4((uint64_t)q, (uint32_t)(col0 + c), k0, k1);
+    const float4 z = omega4_dist((uint64_t)q, (uint32_t)(col0 + c), k0, k1, dist);
     const float zz[4] = {z.x, z.y, z.z, z.w};
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
@@ -202,15 +203,15 @@ hipError_t launch_philox_raw(const uint32_t* ctr, uint64_t seed, uint32_t* out, 
     return hipGetLastError();
 }
 
-hipError_t launch_gen_omega(uint64_t seed, int64_t row0, int64_t n, int64_t col0, int64_t k,
-                            float* Om, int64_t ldo, hipStream_t s) {
+hipError_t launch_gen_omega(uint64_t seed, int dist, int64_t row0, int64_t n, int64_t col0,
+                            int64_t k, float* Om, int64_t ldo, hipStream_t s) {
     if (n == 0 || k == 0) return hipSuccess;
     const int64_t q_lo = row0 >> 2;
     const int64_t nq = ((row0 + n - 1) >> 2) - q_lo + 1;
     const int64_t items = nq * k;
     hipLaunchKernelGGL(k_gen_omega, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, s,
-                       (uint32_t)seed, (uint32_t)(seed >> 32), row0, n, col0, k, Om, ldo, q_lo,
-                       nq);
+                       (uint32_t)seed, (uint32_t)(seed >> 32), dist, row0, n, col0, k, Om, ldo,
+                       q_lo, nq);
     return hipGetLastError();
 }
 

@@ -90,6 +90,7 @@ int validate(const sk_request* r) {
                           r->beta);
     if (st != SK_OK) return st;
     if (r->m < 1 || r->n < 1 || r->k < 1) return SK_EINVAL;
+    if (!dist_ok(r->omega_dist)) return SK_EINVAL;
     if (r->a_source == SK_SRC_DEVICE)
         return check_block(r->A, r->a_dtype, r->m, r->n, r->lda, r->omega_row0, r->a_scales);
     if (r->omega_row0 < 0 || r->omega_row0 > kMaxRow - r->n) return SK_EINVAL;
@@ -206,6 +207,7 @@ void launch_batch(sk_server* S, const sk::Batch& b, const std::vector<ServerReq*
         x.partials = q.partials;
         x.seed = r.seed;
         x.col0 = (uint32_t)r.omega_col0;
+        x.dist = r.omega_dist;
         x.y_f64 = r.y_dtype == SK_Y_F64;
         x.beta = r.beta;
         x.strips = (int32_t)q.g.strips;

@@ -10,7 +10,7 @@ import ctypes
 
 import torch
 
-from . import SK_A_F32, SketchError, _adtype, _ld, _ydtype, lib
+from . import SK_A_F32, SketchError, _adtype, _dist, _ld, _ydtype, lib
 
 SK_SRC_DEVICE, SK_SRC_HOST, SK_SRC_SYNTH = 0, 1, 2
 SK_REQ_QUEUED, SK_REQ_RUNNING, SK_REQ_DONE, SK_REQ_FAILED, SK_REQ_CANCELLED = range(5)
@@ -24,7 +24,7 @@ class SkRequest(ctypes.Structure):
     _fields_ = [("a_source", _int), ("a_dtype", _int), ("A", _vp), ("m", _i64), ("n", _i64),
                 ("lda", _i64), ("a_scales", _vp), ("a_seed", _u64), ("seed", _u64),
                 ("omega_row0", _i64), ("omega_col0", _i64), ("k", _i64), ("Y", _vp),
-                ("y_dtype", _int), ("ldy", _i64), ("beta", _int)]
+                ("y_dtype", _int), ("ldy", _i64), ("beta", _int), ("omega_dist", _int)]
 
 
 class SkTicketInfo(ctypes.Structure):
@@ -76,7 +76,7 @@ def _bind():
 def make_request(*, k: int, seed: int, Y: torch.Tensor, A: torch.Tensor | None = None,
                  m: int | None = None, n: int | None = None, source: int = SK_SRC_DEVICE,
                  a_seed: int = 0, omega_row0: int = 0, omega_col0: int = 0, beta: int = 0,
-                 a_scales: torch.Tensor | None = None) -> SkRequest:
+                 a_scales: torch.Tensor | None = None, dist="normal") -> SkRequest:
     """An sk_request: A a device tensor (SK_SRC_DEVICE), a host tensor (SK_SRC_HOST), or None
     with (m, n) for SK_SRC_SYNTH (A ~ N(0,1) from a_seed, filled by the server)."""
     r = SkRequest()
@@ -102,6 +102,7 @@ def make_request(*, k: int, seed: int, Y: torch.Tensor, A: torch.Tensor | None =
     r.y_dtype = _ydtype(Y.dtype)
     r.ldy = _ld(Y, "Y")
     r.beta = beta
+    r.omega_dist = _dist(dist)
     return r
 
 

@@ -48,7 +48,7 @@ def test_header_symbols_exported():
 
 
 def test_version_and_status_strings():
-    assert sk.sketch_abi_version() == 2
+    assert sk.sketch_abi_version() == 3
     for st in range(-10, 1):
         assert sk.sketch_status_string(st) != "unknown status"
     assert sk.sketch_status_string(-100) == "unknown status"
@@ -135,6 +135,24 @@ def test_other_entry_points_reject():
                                  1 << 30, None) == EINVAL
 
 
+def test_distribution_argument_rejected_on_host():
+    L = sk.lib()
+    for d in (-1, 3):
+        assert L.sketch_gen_matmul_dist(PA, F32, 64, 1024, 1024, None, 1, d, 0, 0, 5, PB, YF32, 5,
+                                        0, PW, 1 << 30, None) == EINVAL
+        assert L.sketch_gen_omega_dist(1, d, 0, 10, 0, 5, PA, 5, None) == EINVAL
+        A = (ctypes.c_void_p * 1)(PA)
+        nb = (ctypes.c_int64 * 1)(1024)
+        r0 = (ctypes.c_int64 * 1)(0)
+        assert L.sketch_gen_matmul_reduce_dist(A, 1, F32, 64, nb, nb, r0, None, 1, d, 0, 5, PB,
+                                               YF32, 5, 0, PW, 1 << 30, None) == EINVAL
+    # valid distributions reach the ordinary argument checks
+    for d in (0, 1, 2):
+        assert L.sketch_gen_matmul_dist(PA, F32, 64, 1024, 1000, None, 1, d, 0, 0, 5, PB, YF32, 5,
+                                        0, PW, 1 << 30, None) == EINVAL      # lda < n
+        assert L.sketch_gen_omega_dist(1, d, 0, 0, 0, 5, None, 5, None) == OK
+
+
 def test_workspace_size_rules():
     ws = sk.sketch_workspace_size
     assert ws(0, F32, 4096, 1024, 5, 1) == 0          # one strip: written directly, no partials
@@ -188,6 +206,7 @@ def test_request_footprint_rule():
     assert fp(req(a_source=sv.SK_SRC_HOST, n=1001, lda=1001, m=3, k=1, ldy=1)) == 12288 + 0
     assert fp(req(a_source=sv.SK_SRC_HOST, n=1001, lda=1001, m=1, k=1, ldy=1)) == 4096
     for bad in (dict(k=0), dict(m=0), dict(n=0), dict(a_source=3), dict(ldy=4), dict(Y=None),
+                dict(omega_dist=3), dict(omega_dist=-1),
                 dict(a_source=sv.SK_SRC_SYNTH), dict(a_source=sv.SK_SRC_SYNTH, A=None, a_dtype=BF16),
                 dict(a_source=sv.SK_SRC_HOST, lda=100), dict(A=PA + 4), dict(a_dtype=FP8)):
         assert fp(req(**bad)) == 0, bad
