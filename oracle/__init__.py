@@ -57,6 +57,9 @@ def _load():
                                                ctypes.c_int, P]
     lib.oracle_gen_matmul_reduce_dist_f64.argtypes = [P, i64, i64, P, P, P, u64, i64, i64,
                                                       ctypes.c_int, P]
+    lib.oracle_gen_matmul_cm_f64.argtypes = [P, i64, i64, i64, u64, i64, i64, i64, ctypes.c_int,
+                                             P]
+    lib.oracle_gen_tmatmul_f64.argtypes = [P, i64, i64, i64, u64, i64, i64, i64, ctypes.c_int, P]
     lib.oracle_omega_f64ref.argtypes = [u64, i64, i64]
     lib.oracle_omega_f64ref.restype = ctypes.c_double
     lib.oracle_omega_block.argtypes = [u64, i64, i64, i64, i64, P]
@@ -185,6 +188,33 @@ def gen_matmul_reduce(blocks, row0s, seed: int, col0: int, k: int, dist="normal"
         _load().oracle_gen_matmul_reduce_dist_f64(ptrs, P, m, _ptr(n_b), _ptr(lda_b), _ptr(r0),
                                                   seed, col0, k, _dist(dist), _ptr(Y))
     return Y
+
+
+def gen_matmul_cm(Acm: np.ndarray, m: int, n: int, lda: int, seed: int, row0: int, col0: int,
+                  k: int, dist="normal") -> np.ndarray:
+    """Y = A * Omega[row0:row0+n, col0:col0+k] (FP64, m x k) for a column-major FP32 A given
+    as its flat storage: element (i, j) at Acm[j * lda + i]."""
+    Acm = np.ascontiguousarray(Acm, dtype=np.float32).ravel()
+    if n > 0 and Acm.size < (n - 1) * lda + m:
+        raise ValueError("A storage too small")
+    Y = np.zeros((m, k), dtype=np.float64)
+    if m and k:
+        _load().oracle_gen_matmul_cm_f64(_ptr(Acm), m, n, lda, seed, row0, col0, k, _dist(dist),
+                                         _ptr(Y))
+    return Y
+
+
+def gen_tmatmul(B: np.ndarray, seed: int, row0: int, col0: int, k: int,
+                dist="normal") -> np.ndarray:
+    """C = Omega[row0:row0+n, col0:col0+k]^T * B (FP64, k x p) for FP32 B (n x p)
+    (Alg. 2's second product)."""
+    B, ldb = _rows(B, np.float32)
+    n, p = B.shape
+    C = np.zeros((k, p), dtype=np.float64)
+    if k and p:
+        _load().oracle_gen_tmatmul_f64(_ptr(B), n, p, ldb, seed, row0, col0, k, _dist(dist),
+                                       _ptr(C))
+    return C
 
 
 def matmul(A: np.ndarray, Om: np.ndarray) -> np.ndarray:

@@ -297,6 +297,51 @@ void oracle_gen_matmul_reduce_f64(const float* const* A_b, int64_t P, int64_t m,
 }
 
 /* ------------------------------------------------------------------ */
+/* Column-major A, and the second Nystrom product.                     */
+/* ------------------------------------------------------------------ */
+/* Y = A * Omega[row0:row0+n, col0:col0+k] with A column-major: element
+ * (i, j) at A[j * lda + i]; Y row-major m x k (FP64). */
+void oracle_gen_matmul_cm_f64(const float* A, int64_t m, int64_t n, int64_t lda, uint64_t seed,
+                              int64_t row0, int64_t col0, int64_t k, int dist, double* Y)
+{
+    if (m <= 0 || k <= 0) return;
+    memset(Y, 0, sizeof(double) * (size_t)(m * k));
+    if (n <= 0) return;
+    float* Om = (float*)malloc(sizeof(float) * (size_t)(n * k));
+    oracle_omega_block_dist(seed, row0, n, col0, k, dist, Om);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t c = 0; c < k; ++c) {
+            double acc = 0.0;
+            for (int64_t j = 0; j < n; ++j)
+                acc += (double)A[j * lda + i] * (double)Om[j * k + c];
+            Y[i * k + c] = acc;
+        }
+    free(Om);
+}
+
+/* Alg. 2's second product: C (k x p, row-major, FP64) =
+ * Omega[row0:row0+n, col0:col0+k]^T * B, B row-major n x p (leading dim ldb). */
+void oracle_gen_tmatmul_f64(const float* B, int64_t n, int64_t p, int64_t ldb, uint64_t seed,
+                            int64_t row0, int64_t col0, int64_t k, int dist, double* C)
+{
+    if (k <= 0 || p <= 0) return;
+    memset(C, 0, sizeof(double) * (size_t)(k * p));
+    if (n <= 0) return;
+    float* Om = (float*)malloc(sizeof(float) * (size_t)(n * k));
+    oracle_omega_block_dist(seed, row0, n, col0, k, dist, Om);
+#pragma omp parallel for schedule(static)
+    for (int64_t a = 0; a < k; ++a)
+        for (int64_t b = 0; b < p; ++b) {
+            double acc = 0.0;
+            for (int64_t j = 0; j < n; ++j)
+                acc += (double)Om[j * k + a] * (double)B[j * ldb + b];
+            C[a * p + b] = acc;
+        }
+    free(Om);
+}
+
+/* ------------------------------------------------------------------ */
 /* Low-precision storage formats.                                      */
 /* ------------------------------------------------------------------ */
 void oracle_bf16_encode(const float* x, uint16_t* out, int64_t N)

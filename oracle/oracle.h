@@ -76,6 +76,15 @@ void oracle_gen_matmul_reduce_dist_f64(const float* const* A_b, int64_t P, int64
                                        const int64_t* row0_b, uint64_t seed, int64_t col0,
                                        int64_t k, int dist, double* Y);
 
+/* Column-major A (element (i, j) at A[j * lda + i]): Y (m x k row-major FP64) =
+ * A * Omega(seed, dist)[row0:row0+n, col0:col0+k]. */
+void oracle_gen_matmul_cm_f64(const float* A, int64_t m, int64_t n, int64_t lda, uint64_t seed,
+                              int64_t row0, int64_t col0, int64_t k, int dist, double* Y);
+/* Alg. 2's second product: C (k x p row-major FP64) =
+ * Omega(seed, dist)[row0:row0+n, col0:col0+k]^T * B (B row-major n x p, leading dim ldb). */
+void oracle_gen_tmatmul_f64(const float* B, int64_t n, int64_t p, int64_t ldb, uint64_t seed,
+                            int64_t row0, int64_t col0, int64_t k, int dist, double* C);
+
 /* Product with an explicit Omega (n x k row-major FP32, leading dim ldo). */
 void oracle_matmul_f64(const float* A, int64_t m, int64_t n, int64_t lda, const float* Om,
                        int64_t ldo, int64_t k, double* Y);

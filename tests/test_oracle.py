@@ -226,6 +226,44 @@ def test_rademacher_product_of_integer_matrix_is_exact():
     assert np.array_equal(Yr, Y)
 
 
+def test_column_major_equals_row_major_of_the_same_matrix():
+    """A stored column-major (with NaN padding below each column that must never be
+    read) gives bitwise the row-major product of the same matrix."""
+    m, n, lda = 37, 500, 40
+    A = normal_matrix(m, n, seed=12)
+    Acm = np.full((n, lda), np.nan, dtype=np.float32)
+    Acm[:, :m] = A.T
+    for dist in ("normal", "uniform", "rademacher"):
+        Y = oracle.gen_matmul_cm(Acm.ravel(), m, n, lda, 5, 9, 2, 7, dist)
+        assert np.array_equal(Y, oracle.gen_matmul(A, 5, 9, 2, 7, dist)), dist
+
+
+def test_second_nystrom_product_definition():
+    """C = Omega^T B: against numpy on the oracle's Omega, against the column-major
+    product of B^T (bitwise: same sums), a one-hot B picking one Omega row, and an
+    exactly rounded sum on a tiny case."""
+    n, p, k = 900, 6, 5
+    B = normal_matrix(n, p, seed=13)
+    C = oracle.gen_tmatmul(B, 3, 11, 4, k)
+    Om = oracle.omega_block(3, 11, n, 4, k).astype(np.float64)
+    assert np.allclose(C, Om.T @ B.astype(np.float64), rtol=1e-12, atol=1e-10)
+    # B row-major n x p is B^T column-major p x n with lda = p
+    Ct = oracle.gen_matmul_cm(B.ravel(), p, n, p, 3, 11, 4, k)
+    assert np.array_equal(C, Ct.T)
+    E = np.zeros((n, p), dtype=np.float32)
+    E[123, 2] = 1.0
+    Ce = oracle.gen_tmatmul(E, 3, 11, 4, k)
+    assert np.array_equal(Ce[:, 2], Om[123])
+    assert not np.delete(Ce, 2, axis=1).any()
+    Bt = normal_matrix(9, 3, seed=14)
+    Ct = oracle.gen_tmatmul(Bt, 8, 1, 0, 2)
+    Omt = oracle.omega_block(8, 1, 9, 0, 2)
+    for a in range(2):
+        for b in range(3):
+            ref = math.fsum(float(Omt[j, a]) * float(Bt[j, b]) for j in range(9))
+            assert abs(Ct[a, b] - ref) <= 1e-15 * max(1.0, abs(ref))
+
+
 def test_omega_block_is_slice_of_global():
     full = oracle.omega_block(9, 0, 300, 0, 40)
     for row0, n, col0, k in [(0, 300, 0, 40), (3, 101, 7, 5), (1, 1, 39, 1), (257, 43, 0, 16)]:
