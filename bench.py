@@ -59,11 +59,12 @@ def parse():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--workload", default="shares",
-                   choices=["shares", "ksweep", "precision", "serve", "dists"],
+                   choices=["shares", "ksweep", "precision", "serve", "dists", "colmajor"],
                    help="shares: the headline step (default); ksweep: 65536x16384, k in "
                         "{5,16,64,256}, generated vs stored Omega; precision: BF16 / FP8 A; "
                         "serve: Poisson stream of uneven requests through the request server; "
-                        "dists: normal / uniform / Rademacher Omega on 32768x32768")
+                        "dists: normal / uniform / Rademacher Omega on 32768x32768; "
+                        "colmajor: column-major A, transposed form, C = Omega^T B")
     p.add_argument("--serve-requests", type=int, default=2000,
                    help="requests of the served stream (also summarised in the default line)")
     p.add_argument("--serve-slots", type=int, default=32, help="server in-flight slots")
@@ -247,6 +248,50 @@ def run_dists(args):
     print(json.dumps(out), flush=True)
 
 
+def run_colmajor(args):
+    """Column-major A (the paper's storage order), the transposed form Omega^T A^T, and
+    Alg. 2's second product C = Omega^T B, on a 32768 x 32768 FP32 A."""
+    import torch
+
+    import paper_2603_20966_amd as sk
+    from sketch_inputs import normal_matrix_device
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    N = 32768
+    A = normal_matrix_device(N, N, seed=0, device=dev)
+    Acm = A.t()                                    # the same bytes read as a column-major A
+    rows = []
+    for k in (5, 16, 64):
+        Y = torch.empty((N, k), device=dev)
+        Yt = torch.empty((k, N), device=dev)
+        t, _ = _timeit(torch, stream, lambda: sk.sketch_gen_matmul_cm(Acm, 1, k, Y=Y, stream=stream),
+                       args.steps)
+        tt, _ = _timeit(torch, stream, lambda: sk.sketch_gen_matmul_cm(Acm, 1, k, Y=Yt, y_trans=True,
+                                                                       stream=stream), args.steps)
+        tr, _ = _timeit(torch, stream, lambda: sk.sketch_gen_matmul(A, 1, k, Y=Y, stream=stream),
+                        args.steps)
+        rows.append({"op": "column-major A * Omega", "k": k, "ms": round(t, 4),
+                     "A_GBps": round(N * N * 4 / (t * 1e-3) / 1e9, 1),
+                     "frac_hbm": round(N * N * 4 / (t * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                     "transposed_form_ms": round(tt, 4), "row_major_same_bytes_ms": round(tr, 4)})
+    for k in (5, 64):
+        B = torch.empty((N, (k + 3) // 4 * 4), device=dev)[:, :k]   # rows 16-byte aligned
+        sk.sketch_gen_matmul(A, 1, k, Y=B, stream=stream)
+        C = torch.empty((k, k), device=dev)
+        t, _ = _timeit(torch, stream, lambda: sk.sketch_gen_tmatmul(B, 1, k, C=C, stream=stream),
+                       args.steps)
+        tb, _ = _timeit(torch, stream, lambda: sk.sketch_gen_matmul(A, 1, k, Y=B, stream=stream),
+                        args.steps)
+        rows.append({"op": "Nystrom C = Omega^T B (B = A Omega, n = 32768)", "k": k,
+                     "ms": round(t, 4), "B_GBps": round(N * k * 4 / (t * 1e-3) / 1e9, 1),
+                     "first_product_ms": round(tb, 4)})
+    out = {"metric": "column-major A GB/s; Nystrom second product time", "unit": "GB/s",
+           "n_gpus": 1, "steps": args.steps, "higher_is_better": True, "dtype": "f32",
+           "data": "synthetic", "config": {"workload": "A 32768x32768 fp32 N(0,1)"}, "rows": rows}
+    print(json.dumps(out), flush=True)
+
+
 def _pct(xs, q):
     import numpy as np
 
@@ -400,6 +445,8 @@ def main():
         return run_serve(args, torch)
     if args.workload == "dists":
         return run_dists(args)
+    if args.workload == "colmajor":
+        return run_colmajor(args)
 
     import paper_2603_20966_amd as sk
     from sketch_inputs import normal_matrix_device

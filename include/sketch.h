@@ -105,6 +105,8 @@ int64_t sketch_strip_width(int a_dtype, int64_t k);
  * (different streams) need separate workspaces.
  *   op = 0: sketch_gen_matmul / sketch_matmul_omega with an n-column A;
  *   op = 1: sketch_gen_matmul_reduce over P blocks whose widths sum to n.
+ *   op = 2: sketch_gen_matmul_cm with an m x n column-major FP32 A (for
+ *           sketch_gen_tmatmul pass m = p, the columns of B).
  * The size depends only on (op, a_dtype, m, n, k, P); for op = 1 it is an
  * upper bound valid for any split of n into P blocks.  Returns 0 for
  * invalid arguments. */
@@ -173,6 +175,42 @@ int sketch_gen_matmul_reduce_dist(const void* const* A_b, int64_t P, int a_dtype
                                   uint64_t seed, int dist, int64_t omega_col0, int64_t k,
                                   void* Y, int y_dtype, int64_t ldy, int beta, void* workspace,
                                   size_t workspace_bytes, void* stream);
+
+/*
+ * Column-major A (the paper's storage order, Sec. 6.1), FP32:
+ *
+ *   Y (=|+=) A * Omega(seed, dist)[row0 : row0+n, col0 : col0+k]
+ *
+ *   A       device, element (i, j) at A + j*lda + i, lda >= m; A and lda*4 must
+ *           be multiples of 16 bytes.
+ *   y_trans 0: Y row-major m x k (element (i, c) at Y + i*ldy + c, ldy >= k);
+ *           1: Y stored transposed, i.e. the k x m matrix Omega^T A^T row-major
+ *           (element (i, c) at Y + c*ldy + i, ldy >= m) -- the transposed form
+ *           of the product (Sec. 4.1 transposition remark).
+ *   Other arguments as for sketch_gen_matmul_dist; workspace:
+ *   sketch_workspace_size(2, SK_A_F32, m, n, k, 1).  The FP32 sums run over
+ *   strips of columns with FP64 strip sums, as in the row-major calls.
+ */
+int sketch_gen_matmul_cm(const float* A, int64_t m, int64_t n, int64_t lda, uint64_t seed,
+                         int dist, int64_t omega_row0, int64_t omega_col0, int64_t k, void* Y,
+                         int y_dtype, int64_t ldy, int y_trans, int beta, void* workspace,
+                         size_t workspace_bytes, void* stream);
+
+/*
+ * The second product of the Nystrom approximation (Alg. 2: B = A Omega, then
+ * C = Omega^T B with the same generated Omega):
+ *
+ *   C (=|+=) Omega(seed, dist)[row0 : row0+n, col0 : col0+k]^T * B
+ *
+ *   B   device, n x p row-major FP32, leading dim ldb (B and ldb*4 multiples of
+ *       16 bytes); C device, k x p row-major (ldc >= p), storage c_dtype.
+ *   Computed as (B^T Omega)^T by sketch_gen_matmul_cm (B row-major is B^T
+ *   column-major); workspace: sketch_workspace_size(2, SK_A_F32, p, n, k, 1).
+ */
+int sketch_gen_tmatmul(const float* B, int64_t n, int64_t p, int64_t ldb, uint64_t seed, int dist,
+                       int64_t omega_row0, int64_t omega_col0, int64_t k, void* C, int c_dtype,
+                       int64_t ldc, int beta, void* workspace, size_t workspace_bytes,
+                       void* stream);
 
 /*
  * Per-phase timing (instrumentation; the paper times each phase separately,

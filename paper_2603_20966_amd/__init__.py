@@ -73,6 +73,10 @@ def lib() -> ctypes.CDLL:
         L.sketch_gen_matmul_reduce_dist.argtypes = [P, i64, i32, i64, P, P, P, P, u64, i32, i64,
                                                     i64, P, i32, i64, i32, P, sz, P]
         L.sketch_gen_omega_dist.argtypes = [u64, i32, i64, i64, i64, i64, P, i64, P]
+        L.sketch_gen_matmul_cm.argtypes = [P, i64, i64, i64, u64, i32, i64, i64, i64, P, i32, i64,
+                                           i32, i32, P, sz, P]
+        L.sketch_gen_tmatmul.argtypes = [P, i64, i64, i64, u64, i32, i64, i64, i64, P, i32, i64,
+                                         i32, P, sz, P]
         L.sketch_matmul_omega.argtypes = [P, i32, i64, i64, i64, P, P, i64, i64, P, i32, i64, i32,
                                           P, sz, P]
         L.sketch_philox_raw.argtypes = [P, u64, P, i64, P]
@@ -80,6 +84,7 @@ def lib() -> ctypes.CDLL:
         L.sketch_trace_events.argtypes = [P, P, P]
         for f in ("sketch_gen_matmul", "sketch_gen_matmul_reduce", "sketch_gen_matmul_dist",
                   "sketch_gen_matmul_reduce_dist", "sketch_gen_omega_dist",
+                  "sketch_gen_matmul_cm", "sketch_gen_tmatmul",
                   "sketch_gen_omega", "sketch_matmul_omega", "sketch_philox_raw",
                   "sketch_quantize", "sketch_trace_events"):
             getattr(L, f).restype = i32
@@ -278,6 +283,59 @@ def sketch_matmul_omega(A: torch.Tensor, Omega: torch.Tensor, *, Y: torch.Tensor
     return Y
 
 
+def sketch_gen_matmul_cm(A: torch.Tensor, seed: int, k: int, *, omega_row0: int = 0,
+                         omega_col0: int = 0, Y: torch.Tensor | None = None, beta: int = 0,
+                         y_trans: bool = False, y_dtype=torch.float32,
+                         workspace: torch.Tensor | None = None, stream=None,
+                         dist="normal") -> torch.Tensor:
+    """Y (=|+=) A * Omega[row0:row0+n, col0:col0+k] for a column-major FP32 A (an m x n
+    tensor with stride (1, lda), e.g. the transpose of a row-major n x m tensor).
+    y_trans: return Omega^T A^T (k x m) instead of Y (m x k)."""
+    m, n = A.shape
+    if A.dtype != torch.float32:
+        raise TypeError("column-major A must be float32")
+    if m > 1 and A.stride(0) != 1:
+        raise ValueError("A must be column-major (stride(0) == 1)")
+    lda = int(A.stride(1)) if n > 1 else max(m, 4)
+    shape = (k, m) if y_trans else (m, k)
+    Y = _out(Y, shape[0], shape[1], y_dtype if Y is None else Y.dtype, A.device)
+    ldy = _ld(Y, "Y") if Y.numel() else max(shape[1], 1)
+    st = _stream(stream, A.device)
+    need = sketch_workspace_size(2, SK_A_F32, m, n, k, 1)
+    if workspace is not None:
+        wsp, wsb = _ptr(workspace), workspace.numel() * workspace.element_size()
+    else:
+        wsp, wsb = workspace_for(need, A.device, st)
+    _check(lib().sketch_gen_matmul_cm(_ptr(A), m, n, lda, seed, _dist(dist), omega_row0,
+                                      omega_col0, k, _ptr(Y), _ydtype(Y.dtype), ldy, int(y_trans),
+                                      beta, wsp, wsb, st), "sketch_gen_matmul_cm")
+    return Y
+
+
+def sketch_gen_tmatmul(B: torch.Tensor, seed: int, k: int, *, omega_row0: int = 0,
+                       omega_col0: int = 0, C: torch.Tensor | None = None, beta: int = 0,
+                       c_dtype=torch.float32, workspace: torch.Tensor | None = None, stream=None,
+                       dist="normal") -> torch.Tensor:
+    """C (=|+=) Omega[row0:row0+n, col0:col0+k]^T * B (k x p) for a row-major FP32 B (n x p):
+    Alg. 2's second product."""
+    n, p = B.shape
+    if B.dtype != torch.float32:
+        raise TypeError("B must be float32")
+    ldb = _ld(B, "B") if n > 0 else max(p, 4)
+    C = _out(C, k, p, c_dtype if C is None else C.dtype, B.device)
+    ldc = _ld(C, "C") if C.numel() else max(p, 1)
+    st = _stream(stream, B.device)
+    need = sketch_workspace_size(2, SK_A_F32, p, n, k, 1)
+    if workspace is not None:
+        wsp, wsb = _ptr(workspace), workspace.numel() * workspace.element_size()
+    else:
+        wsp, wsb = workspace_for(need, B.device, st)
+    _check(lib().sketch_gen_tmatmul(_ptr(B), n, p, ldb, seed, _dist(dist), omega_row0, omega_col0,
+                                    k, _ptr(C), _ydtype(C.dtype), ldc, beta, wsp, wsb, st),
+           "sketch_gen_tmatmul")
+    return C
+
+
 def sketch_philox_raw(ctr: torch.Tensor, seed: int, *, out: torch.Tensor | None = None,
                       stream=None) -> torch.Tensor:
     """Philox4x32-10 of each row of ctr (N x 4 int32/uint32 device tensor) under key = seed."""
@@ -322,6 +380,7 @@ from .serve import SketchServer, make_request, sk_request_footprint  # noqa: E40
 
 __all__ = ["sketch_abi_version", "sketch_status_string", "sketch_workspace_size",
            "sketch_strip_width", "SketchServer", "make_request", "sk_request_footprint",
-           "sketch_gen_matmul", "sketch_gen_matmul_reduce",
+           "sketch_gen_matmul", "sketch_gen_matmul_reduce", "sketch_gen_matmul_cm",
+           "sketch_gen_tmatmul",
            "sketch_gen_omega", "sketch_matmul_omega", "sketch_philox_raw", "sketch_quantize",
            "sketch_trace_events", "SketchError", "lib", "LIB_PATH"]

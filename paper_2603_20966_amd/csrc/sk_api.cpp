@@ -82,8 +82,13 @@ int64_t sketch_strip_width(int a_dtype, int64_t k) {
 }
 
 size_t sketch_workspace_size(int op, int a_dtype, int64_t m, int64_t n, int64_t k, int64_t P) {
-    if ((op != 0 && op != 1) || !adtype_ok(a_dtype) || m < 0 || n < 0 || k < 0 || k > kMaxK)
+    if ((op != 0 && op != 1 && op != 2) || !adtype_ok(a_dtype) || m < 0 || n < 0 || k < 0 ||
+        k > kMaxK)
         return 0;
+    if (op == 2) {   // column-major A (sketch_gen_matmul_cm; sketch_gen_tmatmul with m = p)
+        if (a_dtype != SK_A_F32 || m == 0 || k == 0 || n == 0) return 0;
+        return sk::gemm_workspace_bytes(m, sk::cm_strips(n, k), k);
+    }
     if (op == 0) P = 1;
     if (P < 1 || P > sk::kMaxBlocks || m == 0 || k == 0 || n == 0) return 0;
     return workspace_for(op, a_dtype, m, n, k, P);
@@ -249,6 +254,65 @@ int sketch_gen_omega_dist(uint64_t seed, int dist, int64_t row0, int64_t n, int6
 int sketch_gen_omega(uint64_t seed, int64_t row0, int64_t n, int64_t col0, int64_t k,
                      float* Omega, int64_t ldo, void* stream) {
     return sketch_gen_omega_dist(seed, SK_DIST_NORMAL, row0, n, col0, k, Omega, ldo, stream);
+}
+
+int sketch_gen_matmul_cm(const float* A, int64_t m, int64_t n, int64_t lda, uint64_t seed,
+                         int dist, int64_t omega_row0, int64_t omega_col0, int64_t k, void* Y,
+                         int y_dtype, int64_t ldy, int y_trans, int beta, void* workspace,
+                         size_t workspace_bytes, void* stream) {
+    if (!dist_ok(dist) || (y_trans != 0 && y_trans != 1)) return SK_EINVAL;
+    if (!ydtype_ok(y_dtype)) return SK_EDTYPE;
+    if (m < 0 || n < 0 || k < 0 || k > kMaxK || (beta != 0 && beta != 1)) return SK_EINVAL;
+    if (omega_col0 < 0 || omega_col0 + k > kMaxCol) return SK_EINVAL;
+    if (omega_row0 < 0 || omega_row0 > kMaxRow - n) return SK_EINVAL;
+    if (m == 0 || k == 0) return SK_OK;
+    if (Y == nullptr || ldy < (y_trans ? m : k)) return SK_EINVAL;
+    if (((uintptr_t)Y & (y_dtype == SK_Y_F64 ? 7u : 3u)) != 0) return SK_EALIGN;
+    if (n > 0) {
+        if (A == nullptr || lda < m) return SK_EINVAL;
+        if (!aligned16(A) || (lda * 4) % 16 != 0) return SK_EALIGN;
+    }
+    const int64_t S = n > 0 ? sk::cm_strips(n, k) : 0;
+    const int64_t tiles = S * ((m + 255) / 256) * ((k + sk::kColGroup - 1) / sk::kColGroup);
+    if (tiles > ((int64_t)1 << 31) - 8) return SK_EUNSUPPORTED;
+    int st = check_workspace(S > 1 ? sk::gemm_workspace_bytes(m, S, k) : 0, workspace,
+                             workspace_bytes);
+    if (st != SK_OK) return st;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    if (n == 0) {
+        if (beta) return SK_OK;
+        if (!y_trans) return from_hip(sk::launch_zero_matrix(Y, y_dtype == SK_Y_F64, m, k, ldy, s));
+        return from_hip(sk::launch_zero_matrix(Y, y_dtype == SK_Y_F64, k, m, ldy, s));
+    }
+    sk::CmLaunch g{};
+    g.A = A;
+    g.m = m;
+    g.n = n;
+    g.lda = lda;
+    g.row0 = omega_row0;
+    g.seed = seed;
+    g.dist = dist;
+    g.col0 = (uint32_t)omega_col0;
+    g.k = k;
+    g.Y = Y;
+    g.ldy = ldy;
+    g.y_trans = y_trans;
+    g.y_f64 = (y_dtype == SK_Y_F64);
+    g.beta = beta;
+    g.workspace = workspace;
+    g.stream = s;
+    return from_hip(sk::launch_gemm_cm(g));
+}
+
+int sketch_gen_tmatmul(const float* B, int64_t n, int64_t p, int64_t ldb, uint64_t seed, int dist,
+                       int64_t omega_row0, int64_t omega_col0, int64_t k, void* C, int c_dtype,
+                       int64_t ldc, int beta, void* workspace, size_t workspace_bytes,
+                       void* stream) {
+    // C (k x p) = Omega^T B = (B^T Omega)^T: B row-major n x p is B^T column-major
+    // (p x n, leading dim ldb), and C row-major is (B^T Omega) stored transposed.
+    if (ldc < p && p > 0 && k > 0) return SK_EINVAL;
+    return sketch_gen_matmul_cm(B, p, n, ldb, seed, dist, omega_row0, omega_col0, k, C, c_dtype,
+                                ldc, 1, beta, workspace, workspace_bytes, stream);
 }
 
 int sketch_philox_raw(const uint32_t* ctr, uint64_t seed, uint32_t* out, int64_t N,

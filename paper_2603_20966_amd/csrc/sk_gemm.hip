@@ -488,7 +488,7 @@ __global__ __launch_bounds__(kWgThreads) void k_gemm_batch(const BatchArgs args)
 // Y (=|+=) sum over strips of the FP32 partials, in FP64, strip order fixed;
 // one thread per output element, loads issued 32 at a time.
 __global__ void k_reduce_partials(const float* __restrict__ partials, int S, int64_t m, int64_t k,
-                                  void* Y, int y_f64, int64_t ldy, int beta) {
+                                  void* Y, int y_f64, int64_t ldy, int beta, int y_trans) {
     const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (o >= m * k) return;
     const int64_t r = o / k;
@@ -505,12 +505,13 @@ __global__ void k_reduce_partials(const float* __restrict__ partials, int S, int
         for (int j = 0; j < 32; ++j) y += (double)v[j];
     }
     for (; s < S; ++s) y += (double)p[(int64_t)s * sstride];
+    const int64_t off = y_trans ? c * ldy + r : r * ldy + c;
     if (y_f64) {
-        double* Yp = static_cast<double*>(Y) + r * ldy + c;
+        double* Yp = static_cast<double*>(Y) + off;
         if (beta) y += *Yp;
         *Yp = y;
     } else {
-        float* Yp = static_cast<float*>(Y) + r * ldy + c;
+        float* Yp = static_cast<float*>(Y) + off;
         if (beta) y += (double)*Yp;
         *Yp = (float)y;
     }
@@ -624,11 +625,16 @@ size_t gemm_workspace_bytes(int64_t m, int64_t strips, int64_t k) {
     return (size_t)strips * (size_t)m * (size_t)k * sizeof(float);
 }
 
+hipError_t launch_reduce_partials_t(const float* partials, int S, int64_t m, int64_t k, void* Y,
+                                    int y_f64, int64_t ldy, int beta, int y_trans, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_partials, dim3((unsigned)((m * k + 255) / 256)), dim3(256), 0, s,
+                       partials, S, m, k, Y, y_f64, ldy, beta, y_trans);
+    return hipGetLastError();
+}
+
 hipError_t launch_reduce_partials(const float* partials, int S, int64_t m, int64_t k, void* Y,
                                   int y_f64, int64_t ldy, int beta, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce_partials, dim3((unsigned)((m * k + 255) / 256)), dim3(256), 0, s,
-                       partials, S, m, k, Y, y_f64, ldy, beta);
-    return hipGetLastError();
+    return launch_reduce_partials_t(partials, S, m, k, Y, y_f64, ldy, beta, 0, s);
 }
 
 hipError_t launch_gemm_stream(const GemmLaunch& g) {

@@ -120,6 +120,26 @@ struct BatchArgs {
 int64_t count_strips(const GemmLaunch& g);
 size_t gemm_workspace_bytes(int64_t m, int64_t strips, int64_t k);
 
+// Column-major A (element (i, j) at A + j*lda + i), FP32, generated Omega; Y
+// row-major or transposed (element (i, c) at Y + c*ldy + i).  Strips of
+// cm_strip_width(kclass) columns; partials [S][m][k] as for the other kernels.
+constexpr int cm_strip_width(int kclass) { return kclass <= 8 ? 1024 : 512; }
+struct CmLaunch {
+    const float* A;
+    int64_t m, n, lda, row0;
+    uint64_t seed;
+    int dist;
+    uint32_t col0;
+    int64_t k;
+    void* Y;
+    int64_t ldy;
+    int y_trans, y_f64, beta;
+    void* workspace;
+    hipStream_t stream;
+};
+int64_t cm_strips(int64_t n, int64_t k);
+hipError_t launch_gemm_cm(const CmLaunch& g);
+
 hipError_t launch_gemm_stream(const GemmLaunch& g);
 // Streaming-kernel batch: all requests share the tile class (kclass, adtype);
 // followed by the batched FP64 strip sums.  grid <= 0: one resident round of
@@ -152,6 +172,9 @@ hipError_t launch_fill_normal(float* A, int64_t m, int64_t n, int64_t lda, uint6
                               hipStream_t s);
 hipError_t launch_reduce_partials(const float* partials, int S, int64_t m, int64_t k, void* Y,
                                   int y_f64, int64_t ldy, int beta, hipStream_t s);
+// The same with Y transposed when y_trans (element (i, c) at Y + c*ldy + i).
+hipError_t launch_reduce_partials_t(const float* partials, int S, int64_t m, int64_t k, void* Y,
+                                    int y_f64, int64_t ldy, int beta, int y_trans, hipStream_t s);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_zero_matrix(void* Y, int f64, int64_t m, int64_t k, int64_t ldy, hipStream_t s);
 hipError_t launch_philox_raw(const uint32_t* ctr, uint64_t seed, uint32_t* out, int64_t N,

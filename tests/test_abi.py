@@ -153,6 +153,34 @@ def test_distribution_argument_rejected_on_host():
         assert L.sketch_gen_omega_dist(1, d, 0, 0, 0, 5, None, 5, None) == OK
 
 
+def test_column_major_and_second_product_reject_on_host():
+    L = sk.lib()
+
+    def cm(A=PA, m=300, n=5000, lda=300, dist=0, k=5, Y=PB, ydt=YF32, ldy=5, yt=0, beta=0, ws=PW,
+           wsb=1 << 30):
+        return L.sketch_gen_matmul_cm(A, m, n, lda, 1, dist, 0, 0, k, Y, ydt, ldy, yt, beta, ws,
+                                      wsb, None)
+
+    assert cm(lda=299) == EINVAL                 # lda < m
+    assert cm(lda=302) == EALIGN                 # lda * 4 not a multiple of 16
+    assert cm(A=PA + 4) == EALIGN
+    assert cm(dist=5) == EINVAL and cm(yt=2) == EINVAL and cm(beta=3) == EINVAL
+    assert cm(k=257, ldy=300) == EINVAL
+    assert cm(ldy=4) == EINVAL                   # row-major Y needs ldy >= k
+    assert cm(yt=1, ldy=299) == EINVAL           # transposed Y needs ldy >= m
+    assert cm(ydt=3) == EDTYPE
+    assert cm(ws=None) == EWS
+    assert cm(m=0, A=None, Y=None) == OK and cm(k=0, Y=None) == OK
+    assert L.sketch_gen_tmatmul(PA, 5000, 6, 6, 1, 0, 0, 0, 5, PB, YF32, 5, 0, PW, 1 << 30,
+                                None) == EINVAL                  # ldc < p
+    assert L.sketch_gen_tmatmul(PA, 5000, 6, 6, 1, 0, 0, 0, 5, PB, YF32, 6, 0, PW, 1 << 30,
+                                None) == EALIGN                  # ldb * 4 % 16 != 0
+    ws = sk.sketch_workspace_size
+    assert ws(2, F32, 300, 5000, 5, 1) == 5 * 300 * 5 * 4        # 5 strips of 1024 columns
+    assert ws(2, F32, 300, 1024, 5, 1) == 0 and ws(2, BF16, 300, 5000, 5, 1) == 0
+    assert ws(2, F32, 300, 5000, 16, 1) == 10 * 300 * 16 * 4     # 512-column strips for k > 8
+
+
 def test_workspace_size_rules():
     ws = sk.sketch_workspace_size
     assert ws(0, F32, 4096, 1024, 5, 1) == 0          # one strip: written directly, no partials
