@@ -441,3 +441,32 @@ def test_golden_omega_offsets():
     for r, c, bits in _golden_rows("omega_seed2026_offsets.txt"):
         got = np.float32(oracle.omega_value(2026, int(r), int(c))).view(np.uint32)
         assert int(got) == int(bits, 16)
+
+
+def _rbf(X, sigma):
+    sq = (X * X).sum(1)
+    D = np.maximum(sq[:, None] + sq[None, :] - 2 * X @ X.T, 0.0)
+    return np.exp(-D / (2 * sigma ** 2))
+
+
+def test_nystrom_oracle_closed_forms():
+    """Nystrom approximation (Sec. 5): an exactly rank-q PSD A with q <= r is reproduced;
+    A - A~ is positive semidefinite; with Omega's first r columns contained in the next
+    sketch (column prefix) the error cannot grow."""
+    from oracle.nystrom import nystrom
+
+    rng = np.random.default_rng(4)
+    X = rng.standard_normal((300, 10))
+    A = X @ X.T
+    _, _, At, err = nystrom(A, 20, 7)
+    assert err <= 1e-10
+    Xr = rng.standard_normal((300, 5))
+    K = _rbf(Xr, np.linalg.norm(Xr) / math.sqrt(300))
+    errs = []
+    for r in (8, 16, 32, 64):
+        _, C, At, e = nystrom(K, r, 3)
+        assert np.allclose(C, C.T, rtol=1e-10, atol=1e-10 * np.abs(C).max())
+        assert np.linalg.eigvalsh(K - At).min() >= -1e-9 * np.linalg.norm(K)
+        errs.append(e)
+    assert all(b <= a + 1e-12 for a, b in zip(errs, errs[1:])), errs
+    assert errs[-1] < 0.5 * errs[0]
