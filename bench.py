@@ -59,12 +59,14 @@ def parse():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--workload", default="shares",
-                   choices=["shares", "ksweep", "precision", "serve", "dists", "colmajor"],
+                   choices=["shares", "ksweep", "precision", "serve", "dists", "colmajor",
+                            "nystrom"],
                    help="shares: the headline step (default); ksweep: 65536x16384, k in "
                         "{5,16,64,256}, generated vs stored Omega; precision: BF16 / FP8 A; "
                         "serve: Poisson stream of uneven requests through the request server; "
                         "dists: normal / uniform / Rademacher Omega on 32768x32768; "
-                        "colmajor: column-major A, transposed form, C = Omega^T B")
+                        "colmajor: column-major A, transposed form, C = Omega^T B; "
+                        "nystrom: Nystrom approximation errors and times, n = 32768")
     p.add_argument("--serve-requests", type=int, default=2000,
                    help="requests of the served stream (also summarised in the default line)")
     p.add_argument("--serve-slots", type=int, default=32, help="server in-flight slots")
@@ -292,6 +294,49 @@ def run_colmajor(args):
     print(json.dumps(out), flush=True)
 
 
+def run_nystrom(args):
+    """Nystrom approximation (Sec. 5, Alg. 2) of synthetic 32768 x 32768 PSD kernel
+    matrices (linear kernel of rank-40 data and RBF kernel with sigma = ||X|| / sqrt(n);
+    stand-ins for the paper's CIFAR-10 kernels): relative Frobenius error by rank r, as in
+    the paper's Table 2, and the time of each step."""
+    import torch
+
+    import paper_2603_20966_amd.nystrom as ny
+    from sketch_inputs import kernel_matrix
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    n = 32768
+    rows = []
+    for kind, kw in (("linear", dict(latent=40, dim=256)), ("rbf", dict(latent=8, dim=64))):
+        A = kernel_matrix(kind, n, seed=3, device=dev, **kw)
+        torch.cuda.synchronize()
+        for r in (64, 256):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+            ev[0].record(stream)
+            B, C, Cp = ny.nystrom(A, r, 11, stream=stream)
+            ev[1].record(stream)
+            torch.cuda.synchronize()
+            t_b, _ = _timeit(torch, stream, lambda: ny.sketch_gen_matmul(A, 11, r, Y=B, stream=stream),
+                             args.steps)
+            t_c, _ = _timeit(torch, stream, lambda: ny.sketch_gen_tmatmul(B, 11, r, C=C, stream=stream),
+                             args.steps)
+            t_p, _ = _timeit(torch, stream, lambda: ny.core_pinv(C, ny.default_tol(r)), 3)
+            err = ny.relative_error(A, B, Cp)
+            rows.append({"kernel": kind, "r": r, "rel_fro_error": float(f"{err:.3e}"),
+                         "B_ms": round(t_b, 4), "C_ms": round(t_c, 4), "pinv_ms": round(t_p, 4),
+                         "B_A_GBps": round(n * n * 4 / (t_b * 1e-3) / 1e9, 1)})
+        del A
+        torch.cuda.empty_cache()
+    out = {"metric": "Nystrom relative Frobenius error and step times, n = 32768",
+           "unit": "ms", "n_gpus": 1, "steps": args.steps, "higher_is_better": False,
+           "dtype": "f32 products, f64 core pseudo-inverse", "data": "synthetic",
+           "config": {"workload": "synthetic PSD kernels 32768 x 32768 (linear: data of rank 40; "
+                                  "rbf: sigma = ||X||/sqrt(n)), r in {64, 256}"},
+           "rows": rows}
+    print(json.dumps(out), flush=True)
+
+
 def _pct(xs, q):
     import numpy as np
 
@@ -447,6 +492,8 @@ def main():
         return run_dists(args)
     if args.workload == "colmajor":
         return run_colmajor(args)
+    if args.workload == "nystrom":
+        return run_nystrom(args)
 
     import paper_2603_20966_amd as sk
     from sketch_inputs import normal_matrix_device

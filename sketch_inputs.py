@@ -66,3 +66,41 @@ def request_stream(count: int, seed: int, rate_per_s: float, mn_lo: int = 1024,
         out.append({"id": r, "arrival_s": t, "m": m, "n": n, "k": k,
                     "seed_a": 1_000_000 + r, "seed_omega": 2_000_000 + r})
     return out
+
+
+def kernel_matrix(kind: str, n: int, seed: int, latent: int = 40, dim: int = 256,
+                  noise: float = 0.0, device=None):
+    """Synthetic symmetric PSD kernel matrix (stand-in for the paper's CIFAR-10 kernels,
+    Sec. 6.2): data X = Z W (+ noise), Z n x latent and W latent x dim iid N(0,1), rows of
+    X as samples; kind "linear": A = X X^T (rank <= latent); kind "rbf":
+    A_ij = exp(-|x_i - x_j|^2 / (2 sigma^2)) with sigma = ||X||_F / sqrt(n).
+    FP32 result; numpy on the host, or torch on `device` (generated there)."""
+    if device is None:
+        rng = np.random.default_rng(seed)
+        Z = rng.standard_normal((n, latent))
+        W = rng.standard_normal((latent, dim)) / math.sqrt(latent)
+        X = Z @ W
+        if noise:
+            X += noise * rng.standard_normal((n, dim))
+        if kind == "linear":
+            return (X @ X.T).astype(np.float32)
+        sq = (X * X).sum(1)
+        D = np.maximum(sq[:, None] + sq[None, :] - 2.0 * X @ X.T, 0.0)
+        sigma2 = (X * X).sum() / n
+        return np.exp(-D / (2.0 * sigma2)).astype(np.float32)
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    Z = torch.randn((n, latent), generator=g, device=device, dtype=torch.float32)
+    W = torch.randn((latent, dim), generator=g, device=device, dtype=torch.float32) / math.sqrt(latent)
+    X = Z @ W
+    if noise:
+        X += noise * torch.randn((n, dim), generator=g, device=device, dtype=torch.float32)
+    if kind == "linear":
+        return X @ X.t().contiguous()
+    sq = (X * X).sum(1)
+    sigma2 = (X * X).sum() / n
+    A = X @ X.t().contiguous()
+    A.mul_(-2.0).add_(sq[:, None]).add_(sq[None, :]).clamp_(min=0.0)
+    return A.mul_(-0.5 / sigma2).exp_()
