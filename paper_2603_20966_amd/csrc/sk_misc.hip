@@ -106,15 +106,23 @@ __global__ void k_to_bf16(const float* A, int64_t m, int64_t n, int64_t lda, uin
 }
 
 // max |A| of each 128-row block, as the FP32 bit pattern (monotone for
-// non-negative values), via device-scope atomic max.
+// non-negative values): block (x, b) scans rows [128b, 128b + 128) over a
+// strided set of columns, reduces in registers, the wave and LDS, and issues
+// one device-scope atomic max.
 __global__ void k_amax_rows128(const float* A, int64_t m, int64_t n, int64_t lda, uint32_t* amax) {
-    const int64_t i = blockIdx.y;
+    __shared__ uint32_t wmax[4];
+    const int64_t b = blockIdx.y;
+    const int64_t r_end = min<int64_t>(m, 128 * (b + 1));
     uint32_t mx = 0u;
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
-         j += (int64_t)gridDim.x * blockDim.x)
-        mx = max(mx, __float_as_uint(A[i * lda + j]) & 0x7FFFFFFFu);
+    for (int64_t i = 128 * b; i < r_end; ++i)
+        for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
+             j += (int64_t)gridDim.x * blockDim.x)
+            mx = max(mx, __float_as_uint(A[i * lda + j]) & 0x7FFFFFFFu);
     for (int off = 32; off > 0; off >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, off));
-    if ((threadIdx.x & 63) == 0) atomicMax(&amax[i >> 7], mx);
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        atomicMax(&amax[b], max(max(wmax[0], wmax[1]), max(wmax[2], wmax[3])));
 }
 
 // amax bits -> power-of-two scale 2^E, the smallest with amax <= 448 * 2^E.
@@ -239,9 +247,12 @@ hipError_t launch_quantize(const float* A, int64_t m, int64_t n, int64_t lda, in
     const int64_t nb = (m + 127) / 128;
     hipError_t e = launch_zero(scales, (size_t)nb * sizeof(float), s);
     if (e != hipSuccess) return e;
-    if (n > 0)
-        hipLaunchKernelGGL(k_amax_rows128, grid, dim3(256), 0, s, A, m, n, lda,
+    if (n > 0) {
+        const dim3 g2((unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 64)),
+                      (unsigned)nb);
+        hipLaunchKernelGGL(k_amax_rows128, g2, dim3(256), 0, s, A, m, n, lda,
                            reinterpret_cast<uint32_t*>(scales));
+    }
     hipLaunchKernelGGL(k_fp8_scales, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s,
                        reinterpret_cast<uint32_t*>(scales), nb);
     if (n > 0)
