@@ -6,8 +6,11 @@ of the paper's 1D layouts emulated on one GPU:
   * column layout with reduction: 1 call of sketch_gen_matmul_reduce on 8
     column blocks of 4096 (strided views of A), partial products summed on the
     device in FP64.
-Each step streams A twice (8 GiB).  value = A bytes / wall time of the timed
-steps (GB/s), timed with no per-kernel events.  The roofline object covers the
+Each step streams A twice (8 GiB).  The P share calls are independent (one per
+process of the layout), so a timed step spreads them over two HIP streams, as P
+concurrent processes would run; `extra.sequential_step_GBps` is the same step
+with every call on one stream.  value = A bytes / wall time of the timed steps
+(GB/s), timed with no per-kernel events.  The roofline object covers the
 streaming kernel: algorithmic bytes (A bytes; Omega is generated, never read)
 per launch / launch duration, measured over a second set of the same steps with
 HIP events that the library records on its launch stream just before and after
@@ -77,6 +80,9 @@ def parse():
                    help="also run a plain 1 GiB device copy (known traffic) for counter scaling")
     p.add_argument("--cpu-seconds", type=float, default=10.0,
                    help="minimum duration of the oracle's timed run")
+    p.add_argument("--share-streams", type=int, default=2,
+                   help="streams the P independent shares of a step are spread over (the P "
+                        "processes of the layout run concurrently); 1 = one after another")
     return p.parse_args()
 
 
@@ -525,32 +531,55 @@ def main():
     def arm(ev):
         sk.sketch_trace_events(ev[0].cuda_event, ev[1].cuda_event, ev[2].cuda_event)
 
-    def step(si):
+    # the P shares are independent (one per process of the layout): the timed steps spread
+    # them over `share_streams` streams; the traced steps run them one after another on one
+    # stream, so each kernel's events time that kernel alone
+    ns = max(1, args.share_streams)
+    side = [torch.cuda.Stream(dev) for _ in range(ns - 1)]
+
+    def step(si, nstreams=1):
+        sts = [stream] + side[:nstreams - 1]
+        if nstreams > 1:
+            fork = torch.cuda.Event()
+            fork.record(stream)
+            for st in sts[1:]:
+                st.wait_event(fork)
         for i in range(P):
             if si is not None:
                 arm(trace[si][i])
-            sk.sketch_gen_matmul(shares[i], seed, k, Y=Yrows[i * w:(i + 1) * w], stream=stream)
+            sk.sketch_gen_matmul(shares[i], seed, k, Y=Yrows[i * w:(i + 1) * w],
+                                 stream=sts[i % nstreams])
         if si is not None:
             arm(trace[si][P])
-        sk.sketch_gen_matmul_reduce(blocks, row0s, seed, k, Y=Yred, stream=stream)
+        sk.sketch_gen_matmul_reduce(blocks, row0s, seed, k, Y=Yred, stream=sts[1 % nstreams])
+        for st in sts[1:]:
+            join = torch.cuda.Event()
+            join.record(st)
+            stream.wait_event(join)
 
     for _ in range(args.warmup):
-        step(None)
+        step(None, ns)
     torch.cuda.synchronize()
     same = bool(torch.equal(Yrows, Yred))
-    # timed steps (value): no per-kernel events inside, so nothing perturbs them
-    t_start = torch.cuda.Event(enable_timing=True)
-    t_end = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t_start.record(stream)
-    for _ in range(args.steps):
-        step(None)
-    t_end.record(stream)
-    torch.cuda.synchronize()
-    total_ms = t_start.elapsed_time(t_end)
-    ms_step = total_ms / args.steps
     step_bytes = P * share_bytes + red_bytes
+
+    def timed(nstreams):
+        # no per-kernel events inside, so nothing perturbs the timed steps
+        t_start = torch.cuda.Event(enable_timing=True)
+        t_end = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t_start.record(stream)
+        for _ in range(args.steps):
+            step(None, nstreams)
+        t_end.record(stream)
+        torch.cuda.synchronize()
+        return t_start.elapsed_time(t_end)
+
+    total_ms = timed(ns)
+    ms_step = total_ms / args.steps
     value = step_bytes * args.steps / (total_ms * 1e-3) / 1e9
+    seq_ms = timed(1) if ns > 1 else total_ms
+    seq_value = step_bytes * args.steps / (seq_ms * 1e-3) / 1e9
     # traced steps (roofline): the library records events around each kernel
     for si in range(args.steps):
         step(si)
@@ -590,8 +619,10 @@ def main():
                                "N(0,1) Philox4x32-10 seed 1, k=5; P=8 shares on one GPU: "
                                "row layout (8 x sketch_gen_matmul on 4096-row blocks) + column "
                                "layout (sketch_gen_matmul_reduce on 8 4096-column blocks, "
-                               "FP64 device sum)",
-                   "m": N, "n": N, "k": k, "P": P, "bytes_per_step": step_bytes},
+                               "FP64 device sum); the independent share calls spread over "
+                               f"{ns} stream(s)",
+                   "m": N, "n": N, "k": k, "P": P, "bytes_per_step": step_bytes,
+                   "share_streams": ns},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
                      "traffic": measured_traffic(P, 1),
@@ -600,6 +631,8 @@ def main():
                      "launches": n_launch,
                      "avg_launch_us": round(1e3 * tot_ms / n_launch, 2)},
         "extra": {"hbm_frac_of_value": round(value / HBM_PEAK_GBPS, 4),
+                  "sequential_step_GBps": round(seq_value, 1),
+                  "sequential_ms_per_step": round(seq_ms / args.steps, 4),
                   "row_layout_GBps": round(rate["row"], 1),
                   "col_layout_GBps": round(rate["col"], 1),
                   "row_kernel_us": round(avg_us["row"], 2),
