@@ -369,13 +369,17 @@ __global__ __launch_bounds__(kThreads) void k_gemm_mfma_batch(const BatchArgs ar
 // two BF16 terms, hi = bf16(w) and lo = bf16(w - hi), and each step runs two
 // MFMAs (A*hi, then A*lo): |w - hi - lo| <= 2^-16 |w|, far below the storage
 // error of A, so the product carries A's quantisation only.  The workgroup
-// is W waves x 64 rows sharing each generated Omega chunk (64 contraction
-// columns): the more rows, the less generation per A element, which matters
+// is W waves x 64 rows sharing each generated Omega chunk (a run of
+// contraction columns): the more rows, the less generation per A element, which matters
 // because a byte of FP8 holds four times the elements of a byte of FP32.
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
-constexpr int kLpKC = 64;            // contraction columns per chunk
-constexpr int kLpRow = kLpKC + 8;    // bf16 per LDS column (chunk + 8 pad)
+// Contraction columns per chunk: 128 bytes of every row (BF16: 64 columns,
+// FP8: 128), 32 bytes per lane, so a row is read in whole 128-byte lines
+// (measured: 64-byte runs cost FP8 a quarter of its rate; 256-byte runs gain
+// nothing and cost registers).
+constexpr int lp_kc(int adt) { return adt == 2 ? 128 : 64; }
+constexpr int lp_row(int adt) { return lp_kc(adt) + 8; }   // bf16 per LDS column (+8 pad)
 static_assert(64 * kLpBatchWaves == kLpBatchRows, "batch tile rows");
 
 __device__ __forceinline__ uint32_t bf16_rne_bits(float x) {
@@ -399,11 +403,16 @@ __device__ __forceinline__ void fp8x4_to_bf16(uint32_t w, uint32_t& lo2, uint32_
 }
 
 template <int NT, int ADT, int W, bool GEN>
-__device__ __forceinline__ void lp_tile(const MTile& t, uint16_t (*oh)[16 * NT][kLpRow],
-                                        uint16_t (*ol)[16 * NT][kLpRow]) {
+__device__ __forceinline__ void lp_tile(const MTile& t, uint16_t (*oh)[16 * NT][lp_row(ADT)],
+                                        uint16_t (*ol)[16 * NT][lp_row(ADT)]) {
     constexpr int BN = 16 * NT;
     constexpr int TH = 64 * W;
+    constexpr int KC = lp_kc(ADT);
+    constexpr int KG = KC / 4;            // columns of a lane group per chunk
+    constexpr int V = KC / 32;            // MFMA steps per chunk
     constexpr int es = ADT == 1 ? 2 : 1;
+    constexpr int RW = 2;                 // 16-byte raw A words per lane and M-tile
+    static_assert(KG * es == 16 * RW && kLpStrip % KC == 0, "chunk geometry");
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
@@ -411,36 +420,35 @@ __device__ __forceinline__ void lp_tile(const MTile& t, uint16_t (*oh)[16 * NT][
     const int i16 = lane & 15;
 
     const int w = (int)min<int64_t>(kLpStrip, t.n - t.col_begin);
-    const int nchunks = (w + kLpKC - 1) / kLpKC;
+    const int nchunks = (w + KC - 1) / KC;
     const int64_t row_base = t.block_row + wave * (kTM * 16);
     const int kb = (int)min<int64_t>(BN, t.k - t.n_base);
 
-    // ---- A: lane (g, i) holds columns kc + 16g .. kc + 16g + 15 of row i --------
+    // ---- A: lane (g, i) holds columns kc + KG g .. kc + KG g + KG - 1 of row i ------
     const int64_t ldab = t.lda * es;
     const unsigned char* arow[kTM];
 #pragma unroll
     for (int tm = 0; tm < kTM; ++tm) {
         const int64_t r = min<int64_t>(row_base + tm * 16 + i16, t.m - 1);
-        arow[tm] = t.A + r * ldab + (t.col_begin + 16 * g) * es;
+        arow[tm] = t.A + r * ldab + (t.col_begin + KG * g) * es;
     }
-    // raw A of a chunk: 32 bytes (BF16) or 16 bytes (FP8) per lane and M-tile;
-    // FP8 is widened to BF16 only when the chunk is consumed, so the loads stay
-    // in flight behind the current chunk's MFMAs
-    constexpr int RW = ADT == 1 ? 2 : 1;
+    // raw A of a chunk, RW words per lane and M-tile; FP8 is widened to BF16
+    // only when the chunk is consumed, so the loads stay in flight behind the
+    // current chunk's MFMAs
     auto load_a = [&](v4u (*a)[RW], int c) {
         if (c >= nchunks) return;
-        const int kl = c * kLpKC + 16 * g;
+        const int kl = c * KC + KG * g;
 #pragma unroll
         for (int tm = 0; tm < kTM; ++tm) {
-            const unsigned char* p = arow[tm] + (int64_t)c * kLpKC * es;
-            if (kl + 15 < w) {
+            const unsigned char* p = arow[tm] + (int64_t)c * KC * es;
+            if (kl + KG - 1 < w) {
 #pragma unroll
                 for (int v = 0; v < RW; ++v) a[tm][v] = *reinterpret_cast<const v4u*>(p + 16 * v);
             } else {
                 uint32_t wd[4 * RW];
 #pragma unroll
                 for (int q = 0; q < 4 * RW; ++q) wd[q] = 0u;
-                for (int e = 0; e < 16; ++e) {
+                for (int e = 0; e < KG; ++e) {
                     if (kl + e < w) {
                         const uint32_t v = ADT == 1 ? (uint32_t)reinterpret_cast<const uint16_t*>(p)[e]
                                                     : (uint32_t)p[e];
@@ -454,23 +462,23 @@ __device__ __forceinline__ void lp_tile(const MTile& t, uint16_t (*oh)[16 * NT][
             }
         }
     };
-    // the two 8-element BF16 operands of an M-tile
-    auto operands = [&](const v4u* raw, v4u* op) {
+    // the 8-element BF16 operand of MFMA step v (columns KG g + 8v .. + 7 of the lane)
+    auto operand = [&](const v4u* raw, int v) -> v4u {
         if constexpr (ADT == 1) {
-            op[0] = raw[0];
-            op[1] = raw[1];
+            return raw[v];
         } else {
-            uint32_t o[8];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) fp8x4_to_bf16(raw[0][q], o[2 * q], o[2 * q + 1]);
-            op[0] = v4u{o[0], o[1], o[2], o[3]};
-            op[1] = v4u{o[4], o[5], o[6], o[7]};
+            const v4u r = raw[v >> 1];     // 16 FP8 = two steps per word
+            const int q = 2 * (v & 1);
+            uint32_t o[4];
+            fp8x4_to_bf16(r[q], o[0], o[1]);
+            fp8x4_to_bf16(r[q + 1], o[2], o[3]);
+            return v4u{o[0], o[1], o[2], o[3]};
         }
     };
 
     // ---- Omega chunk -> LDS as (hi, lo) ------------------------------------------
-    for (int it = tid; it < 2 * BN * kLpRow; it += TH) {
-        const int n = (it / kLpRow) % BN;
+    for (int it = tid; it < 2 * BN * lp_row(ADT); it += TH) {
+        const int n = (it / lp_row(ADT)) % BN;
         if (n >= kb) {
             (&oh[0][0][0])[it] = 0;
             (&ol[0][0][0])[it] = 0;
@@ -478,11 +486,11 @@ __device__ __forceinline__ void lp_tile(const MTile& t, uint16_t (*oh)[16 * NT][
     }
     auto make_chunk = [&](int c) {
         const int buf = c & 1;
-        const int kvalid = min(kLpKC, w - c * kLpKC);
+        const int kvalid = min(KC, w - c * KC);
         if constexpr (GEN) {
-            const int64_t g0 = t.row0 + t.col_begin + (int64_t)c * kLpKC;
+            const int64_t g0 = t.row0 + t.col_begin + (int64_t)c * KC;
             const int64_t q_lo = g0 >> 2;
-            const int nq = (int)(((g0 + kLpKC - 1) >> 2) - q_lo + 1);
+            const int nq = (int)(((g0 + KC - 1) >> 2) - q_lo + 1);
             const int items = nq * kb;
             for (int it = tid; it < items; it += TH) {
                 const int qi = it / kb;
@@ -494,7 +502,7 @@ __device__ __forceinline__ void lp_tile(const MTile& t, uint16_t (*oh)[16 * NT][
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const int kl = kl0 + u;
-                    if (kl >= 0 && kl < kLpKC) {
+                    if (kl >= 0 && kl < KC) {
                         uint16_t h = 0, l = 0;
                         if (kl < kvalid) split_bf16(zz[u], h, l);
                         oh[buf][n][kl] = h;
@@ -503,12 +511,12 @@ __device__ __forceinline__ void lp_tile(const MTile& t, uint16_t (*oh)[16 * NT][
                 }
             }
         } else {
-            for (int it = tid; it < kLpKC * kb; it += TH) {
+            for (int it = tid; it < KC * kb; it += TH) {
                 const int kl = it / kb;
                 const int n = it - kl * kb;
                 uint16_t h = 0, l = 0;
                 if (kl < kvalid)
-                    split_bf16(t.omega[(t.col_begin + (int64_t)c * kLpKC + kl) * t.ldo + t.n_base + n],
+                    split_bf16(t.omega[(t.col_begin + (int64_t)c * KC + kl) * t.ldo + t.n_base + n],
                                h, l);
                 oh[buf][n][kl] = h;
                 ol[buf][n][kl] = l;
@@ -530,18 +538,18 @@ __device__ __forceinline__ void lp_tile(const MTile& t, uint16_t (*oh)[16 * NT][
 
     auto compute = [&](v4u (*a)[RW], int c) {
         const int buf = c & 1;
-        v4u op[kTM][2];
 #pragma unroll
-        for (int tm = 0; tm < kTM; ++tm) operands(a[tm], op[tm]);
+        for (int v = 0; v < V; ++v) {
+            v4u op[kTM];
 #pragma unroll
-        for (int v = 0; v < 2; ++v) {
+            for (int tm = 0; tm < kTM; ++tm) op[tm] = operand(a[tm], v);
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
-                const v4u bh = *reinterpret_cast<const v4u*>(&oh[buf][nt * 16 + i16][16 * g + 8 * v]);
-                const v4u bl = *reinterpret_cast<const v4u*>(&ol[buf][nt * 16 + i16][16 * g + 8 * v]);
+                const v4u bh = *reinterpret_cast<const v4u*>(&oh[buf][nt * 16 + i16][KG * g + 8 * v]);
+                const v4u bl = *reinterpret_cast<const v4u*>(&ol[buf][nt * 16 + i16][KG * g + 8 * v]);
 #pragma unroll
                 for (int tm = 0; tm < kTM; ++tm) {
-                    const v8bf av = __builtin_bit_cast(v8bf, op[tm][v]);
+                    const v8bf av = __builtin_bit_cast(v8bf, op[tm]);
                     acc[tm][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
                         av, __builtin_bit_cast(v8bf, bh), acc[tm][nt], 0, 0, 0);
                     acc[tm][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
@@ -567,10 +575,16 @@ __device__ __forceinline__ void lp_tile(const MTile& t, uint16_t (*oh)[16 * NT][
 }
 
 // One call: grid (strips of all blocks, 64W-row tiles, sketch-column blocks).
+// One-N-tile, 4-wave workgroups are kept within 128 registers so that four of
+// them share a compute unit (a 32768-row FP8 launch is exactly four per unit;
+// with three, a quarter of the tiles run as a tail on an underfilled chip).
+constexpr int lp_min_waves(int nt, int w) { return nt == 1 && w == 4 ? 4 : 1; }
+
 template <int NT, int ADT, int W, bool GEN>
-__global__ __launch_bounds__(64 * W) void k_gemm_mfma_lp(const MArgs args) {
-    __shared__ uint16_t oh[2][16 * NT][kLpRow];
-    __shared__ uint16_t ol[2][16 * NT][kLpRow];
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(lp_min_waves(NT, W))))
+void k_gemm_mfma_lp(const MArgs args) {
+    __shared__ uint16_t oh[2][16 * NT][lp_row(ADT)];
+    __shared__ uint16_t ol[2][16 * NT][lp_row(ADT)];
     const int strip = blockIdx.x;
     int b = 0;
     int64_t sib = strip;
@@ -610,8 +624,8 @@ __global__ __launch_bounds__(64 * W) void k_gemm_mfma_lp(const MArgs args) {
 // Batch of requests of one class (serving); rows per tile = kLpBatchRows.
 template <int NT, int ADT>
 __global__ __launch_bounds__(64 * kLpBatchWaves) void k_gemm_mfma_lp_batch(const BatchArgs args) {
-    __shared__ uint16_t oh[2][16 * NT][kLpRow];
-    __shared__ uint16_t ol[2][16 * NT][kLpRow];
+    __shared__ uint16_t oh[2][16 * NT][lp_row(ADT)];
+    __shared__ uint16_t ol[2][16 * NT][lp_row(ADT)];
     const int64_t T8 = (args.total_tiles + 7) / 8;
     bool first = true;
     for (int64_t v = blockIdx.x; v < 8 * T8; v += gridDim.x) {   // gridDim.x is a multiple of 8
@@ -663,11 +677,7 @@ hipError_t launch_lp(const MArgs& a, dim3 grid, hipStream_t s) {
 
 template <int NT, int ADT, bool GEN>
 hipError_t dispatch_lp_w(int waves, const MArgs& a, dim3 grid, hipStream_t s) {
-    switch (waves) {
-    case 4: return launch_lp<NT, ADT, 4, GEN>(a, grid, s);
-    case 8: return launch_lp<NT, ADT, 8, GEN>(a, grid, s);
-    default: return launch_lp<NT, ADT, 16, GEN>(a, grid, s);
-    }
+    return waves == 4 ? launch_lp<NT, ADT, 4, GEN>(a, grid, s) : launch_lp<NT, ADT, 8, GEN>(a, grid, s);
 }
 
 template <int ADT, bool GEN>
