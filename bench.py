@@ -270,7 +270,7 @@ def run_colmajor(args):
     A = normal_matrix_device(N, N, seed=0, device=dev)
     Acm = A.t()                                    # the same bytes read as a column-major A
     rows = []
-    for k in (5, 16, 64):
+    for k in (5, 16, 64, 256):
         Y = torch.empty((N, k), device=dev)
         Yt = torch.empty((k, N), device=dev)
         t, _ = _timeit(torch, stream, lambda: sk.sketch_gen_matmul_cm(Acm, 1, k, Y=Y, stream=stream),

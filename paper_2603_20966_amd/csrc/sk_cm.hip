@@ -13,7 +13,8 @@
 // column is a broadcast read from LDS.  At the end waves 1..3 hand their sums
 // to wave 0 through LDS, which adds them in wave order and writes the strip
 // partial.  The FP64 strip sum is the shared reduction kernel, so results do
-// not depend on the tile grid.
+// not depend on the tile grid.  This kernel serves k <= 16; wider sketches go
+// to the matrix cores (k_gemm_cm_mfma), which read A once for all k.
 #include <algorithm>
 
 #include "sk_device.hpp"
@@ -201,12 +202,18 @@ hipError_t launch_cm_k(const CmArgs& a, hipStream_t s) {
 
 }  // namespace
 
+// Matrix-core kernel for k > 16 (sk_mfma.hip): one pass over A, strips of
+// kMfmaStrip columns.
+hipError_t launch_gemm_cm_mfma(const CmLaunch& g);
+
 int64_t cm_strips(int64_t n, int64_t k) {
-    const int64_t C = cm_strip_width(k_class((int)std::min<int64_t>(k, kColGroup)));
+    const int64_t C = k > kColGroup ? kMfmaStrip
+                                    : cm_strip_width(k_class((int)std::min<int64_t>(k, kColGroup)));
     return (n + C - 1) / C;
 }
 
 hipError_t launch_gemm_cm(const CmLaunch& g) {
+    if (g.k > kColGroup) return launch_gemm_cm_mfma(g);
     const int kc = k_class((int)std::min<int64_t>(g.k, kColGroup));
     const int64_t S = cm_strips(g.n, g.k);
     const int64_t ncg = (g.k + kColGroup - 1) / kColGroup;

@@ -136,11 +136,102 @@ __device__ __forceinline__ void store_tile(const MTile& t, const v4f (&acc)[kTM]
     }
 }
 
+// Columns past k of both LDS halves (BN sketch columns x KC + 4 floats) are
+// zeroed once: generation never writes them.
+template <int BN, int KC>
+__device__ __forceinline__ void omega_zero_pad(float (*om)[BN][KC + 4], int kb) {
+    for (int it = threadIdx.x; it < 2 * BN * (KC + 4); it += kThreads) {
+        const int n = (it / (KC + 4)) % BN;
+        if (n >= kb) (&om[0][0][0])[it] = 0.0f;
+    }
+}
+
+// Omega rows of chunk c of the tile's strip (kvalid of them; zeros past the
+// strip's end) for sketch columns n_base .. n_base + kb - 1 -> LDS half c & 1,
+// laid out [column][contraction]; generated from the seed, or read from a
+// stored Omega.
+template <int BN, int kKC, bool GEN>
+__device__ __forceinline__ void omega_chunk(const MTile& t, float (*om)[BN][kKC + 4], int c, int w,
+                                            int kb) {
+    const int tid = threadIdx.x;
+    const int nthr = kThreads;
+    const int buf = c & 1;
+    const int kvalid = min(kKC, w - c * kKC);
+    if constexpr (GEN) {
+        const int64_t g0 = t.row0 + t.col_begin + (int64_t)c * kKC;  // global Omega row of local 0
+        const int64_t q_lo = g0 >> 2;
+        const int nq = (int)(((g0 + kKC - 1) >> 2) - q_lo + 1);       // KC/4, or one more if unaligned
+        const int items = nq * kb;
+        for (int it = tid; it < items; it += nthr) {
+            const int qi = it / kb;
+            const int n = it - qi * kb;
+            const float4 z = omega4_dist((uint64_t)(q_lo + qi), t.col0 + (uint32_t)(t.n_base + n),
+                                         t.key0, t.key1, t.dist);
+            const int kl0 = (int)(4 * (q_lo + qi) - g0);
+            if (kl0 >= 0 && (kl0 & 3) == 0 && kl0 + 3 < kvalid) {
+                *reinterpret_cast<float4*>(&om[buf][n][kl0]) = z;
+            } else {
+                const float zz[4] = {z.x, z.y, z.z, z.w};
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int kl = kl0 + u;
+                    if (kl >= 0 && kl < kKC) om[buf][n][kl] = (kl < kvalid) ? zz[u] : 0.0f;
+                }
+            }
+        }
+    } else {
+        for (int it = tid; it < kKC * kb; it += nthr) {
+            const int kl = it / kb;
+            const int n = it - kl * kb;
+            om[buf][n][kl] = (kl < kvalid)
+                                 ? t.omega[(t.col_begin + (int64_t)c * kKC + kl) * t.ldo + t.n_base + n]
+                                 : 0.0f;
+        }
+    }
+}
+
+// Chunks c0 .. c0 + G - 1 (those below nchunks) of the tile's strip, generated
+// together into LDS slots slot0 .. slot0 + G - 1 (each laid out as above): with
+// few sketch columns one chunk has too few Philox quads to occupy the
+// workgroup, G of them do.  A chunk's first Omega row is aligned as the strip's
+// (chunk widths are multiples of 4), so every chunk has the same quad count.
+template <int BN, int kKC, int G>
+__device__ __forceinline__ void omega_group(const MTile& t, float (*om)[BN][kKC + 4], int slot0,
+                                            int c0, int nchunks, int w, int kb) {
+    const int64_t gb = t.row0 + t.col_begin;                       // Omega row of strip column 0
+    const int nq = (int)(((gb + kKC - 1) >> 2) - (gb >> 2) + 1);   // quads per chunk
+    const int per = nq * kb;
+    const int cnt = min(G, nchunks - c0);
+    for (int it = threadIdx.x; it < cnt * per; it += kThreads) {
+        const int ci = it / per;
+        const int r = it - ci * per;
+        const int qi = r / kb;
+        const int n = r - qi * kb;
+        const int c = c0 + ci;
+        const int64_t g0 = gb + (int64_t)c * kKC;
+        const int kvalid = min(kKC, w - c * kKC);
+        const int64_t q = (g0 >> 2) + qi;
+        const float4 z = omega4_dist((uint64_t)q, t.col0 + (uint32_t)(t.n_base + n), t.key0, t.key1,
+                                     t.dist);
+        const int kl0 = (int)(4 * q - g0);
+        float* dst = om[slot0 + ci][n];
+        if (kl0 >= 0 && (kl0 & 3) == 0 && kl0 + 3 < kvalid) {
+            *reinterpret_cast<float4*>(&dst[kl0]) = z;
+        } else {
+            const float zz[4] = {z.x, z.y, z.z, z.w};
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int kl = kl0 + u;
+                if (kl >= 0 && kl < kKC) dst[kl] = (kl < kvalid) ? zz[u] : 0.0f;
+            }
+        }
+    }
+}
+
 template <int NT, bool GEN>
 __device__ __forceinline__ void mfma_tile(const MTile& t, float (*om)[16 * NT][lds_row(NT)]) {
     constexpr int BN = 16 * NT;
     constexpr int kKC = chunk_cols(NT);
-    constexpr int kLdsRow = lds_row(NT);
     constexpr int kLV = kKC / 16;   // 16-byte A loads per lane per M-tile per chunk
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -185,46 +276,8 @@ __device__ __forceinline__ void mfma_tile(const MTile& t, float (*om)[16 * NT][l
     };
 
     // ---- Omega chunk -> LDS ----------------------------------------------------------
-    // zero the columns past k once: generation never writes them
-    for (int it = tid; it < 2 * BN * kLdsRow; it += kThreads) {
-        const int n = (it / kLdsRow) % BN;
-        if (n >= kb) (&om[0][0][0])[it] = 0.0f;
-    }
-    auto make_chunk = [&](int c) {
-        const int buf = c & 1;
-        const int kvalid = min(kKC, w - c * kKC);
-        if constexpr (GEN) {
-            const int64_t g0 = t.row0 + t.col_begin + (int64_t)c * kKC;  // global Omega row of local 0
-            const int64_t q_lo = g0 >> 2;
-            const int nq = (int)(((g0 + kKC - 1) >> 2) - q_lo + 1);       // KC/4, or one more if unaligned
-            const int items = nq * kb;
-            for (int it = tid; it < items; it += kThreads) {
-                const int qi = it / kb;
-                const int n = it - qi * kb;
-                const float4 z = omega4_dist((uint64_t)(q_lo + qi), t.col0 + (uint32_t)(n_base + n),
-                                             t.key0, t.key1, t.dist);
-                const int kl0 = (int)(4 * (q_lo + qi) - g0);
-                if (kl0 >= 0 && (kl0 & 3) == 0 && kl0 + 3 < kvalid) {
-                    *reinterpret_cast<float4*>(&om[buf][n][kl0]) = z;
-                } else {
-                    const float zz[4] = {z.x, z.y, z.z, z.w};
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const int kl = kl0 + u;
-                        if (kl >= 0 && kl < kKC) om[buf][n][kl] = (kl < kvalid) ? zz[u] : 0.0f;
-                    }
-                }
-            }
-        } else {
-            for (int it = tid; it < kKC * kb; it += kThreads) {
-                const int kl = it / kb;
-                const int n = it - kl * kb;
-                om[buf][n][kl] = (kl < kvalid)
-                                     ? t.omega[(t.col_begin + (int64_t)c * kKC + kl) * t.ldo + n_base + n]
-                                     : 0.0f;
-            }
-        }
-    };
+    omega_zero_pad<BN, kKC>(om, kb);
+    auto make_chunk = [&](int c) { omega_chunk<BN, kKC, GEN>(t, om, c, w, kb); };
 
     v4f acc[kTM][NT];
 #pragma unroll
@@ -361,6 +414,202 @@ __global__ __launch_bounds__(kThreads) void k_gemm_mfma_batch(const BatchArgs ar
         first = false;
         mfma_tile<NT, true>(t, om);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Column-major A (element (i, j) at A + j*lda + i, the paper's storage order) on
+// the same matrix cores, for k > 16.  The tile computes the transposed product
+// Y^T = Omega^T A^T: the Omega chunk in LDS (same layout and same reads as the
+// B operand above) is the A operand, and A enters as the B operand straight
+// from HBM.  Lane (g, j) loads 16 bytes, rows 4j .. 4j + 3 of one column (a
+// wave reads 256 contiguous bytes of each of four columns per load); component
+// q of the load feeds the MFMA of row set {4j + q}, so a wave holds four 16 x 16
+// accumulator tiles of Y^T per N-tile, covering 64 rows.  Step s of a chunk
+// reads column kc + g*KC/4 + s, the column that contraction index g of step s
+// stands for in the row-major kernel: both kernels form the same products in
+// the same order, and every A element is read once for all k sketch columns.
+struct CmMArgs {
+    const float* A;
+    int64_t m, n, lda, row0;
+    uint32_t key0, key1, col0;
+    int dist;
+    int64_t k;
+    void* Y;
+    int64_t ldy;
+    int y_trans, y_f64, beta;
+    float* partials;
+    int S;                 // strips of kMfmaStrip columns
+    int num_rb;            // 512-row tiles
+    int64_t tiles, tiles8;
+};
+
+// KC = the row-major kernel's chunk for this k (chunk_cols(mfma_ntiles(k))),
+// whatever N-tile count the launch picked, so that the sums are the same.
+template <int NT, int kKC>
+__global__ __launch_bounds__(kThreads) void k_gemm_cm_mfma(const CmMArgs a) {
+    constexpr int BN = 16 * NT;
+    constexpr int kNS = kKC / 4;     // MFMA steps (and 16-byte loads per lane) per chunk
+    constexpr int kLV = kKC / 16;    // 16-byte Omega reads per lane and N-tile per chunk
+    // chunks generated per barrier: enough quads for every thread (1 when BN*KC/4 >= 512)
+    constexpr int kG = kThreads / (kNS * BN) > 1 ? kThreads / (kNS * BN) : 1;
+    static_assert(kG == 1 || kG % 2 == 0, "chunk pairs per generation group");
+    __shared__ float om[2 * kG][BN][kKC + 4];
+
+    const int64_t id = blockIdx.x;
+    const int64_t tt = (id % 8) * a.tiles8 + id / 8;       // XCD-grouped tile order
+    if (tt >= a.tiles) return;
+    const int strip = (int)(tt % a.S);
+    const int rb = (int)((tt / a.S) % a.num_rb);
+    const int nb = (int)(tt / ((int64_t)a.S * a.num_rb));
+
+    MTile t{};
+    t.row0 = a.row0;
+    t.col_begin = (int64_t)strip * kMfmaStrip;
+    t.n_base = nb * BN;
+    t.key0 = a.key0;
+    t.key1 = a.key1;
+    t.col0 = a.col0;
+    t.dist = a.dist;
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int g = lane >> 4;
+    const int j = lane & 15;
+    const int w = (int)min<int64_t>(kMfmaStrip, a.n - t.col_begin);
+    const int nchunks = (w + kKC - 1) / kKC;
+    const int kb = (int)min<int64_t>(BN, a.k - t.n_base);
+    const int64_t r0 = (int64_t)rb * kBM + wave * 64;      // first row of the wave
+    const int64_t rl = r0 + 4 * j;                          // first row of the lane
+    const bool active = r0 < a.m;                           // the wave has rows
+    const bool full_rows = rl + 3 < a.m;
+
+    // ---- A loads: step s of chunk c is column col_begin + c*KC + g*KC/4 + s --------
+    const float* acol = a.A + (t.col_begin + g * kNS) * a.lda + rl;
+    auto load_a = [&](v4f* x, int c) {
+        if (!active || c >= nchunks) return;
+        const int kl = c * kKC + g * kNS;
+#pragma unroll
+        for (int s = 0; s < kNS; ++s) {
+            const float* p = acol + (int64_t)(c * kKC + s) * a.lda;
+            if (full_rows && kl + s < w) {
+                x[s] = *reinterpret_cast<const v4f*>(p);
+            } else {
+                v4f v = {0.f, 0.f, 0.f, 0.f};
+                if (kl + s < w)
+                    for (int q = 0; q < 4; ++q)
+                        if (rl + q < a.m) v[q] = p[q];
+                x[s] = v;
+            }
+        }
+    };
+
+    omega_zero_pad<BN, kKC>(om, kb);
+    v4f acc[4][NT];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[q][nt] = v4f{0.f, 0.f, 0.f, 0.f};
+
+    v4f a0[kNS], a1[kNS];
+    load_a(a0, 0);
+    load_a(a1, 1);
+    omega_group<BN, kKC, kG>(t, om, 0, 0, nchunks, w, kb);
+    lds_barrier_m();
+
+    auto compute = [&](const v4f* x, int buf) {
+        if (!active) return;
+        v4f wop[NT][kLV];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int v = 0; v < kLV; ++v)
+                wop[nt][v] = *reinterpret_cast<const v4f*>(&om[buf][nt * 16 + j][4 * kLV * g + 4 * v]);
+#pragma unroll
+        for (int v = 0; v < kLV; ++v)
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt)
+                        acc[q][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                            wop[nt][v][s], x[4 * v + s][q], acc[q][nt], 0, 0, 0);
+    };
+
+    if constexpr (kG == 1) {
+        for (int c = 0; c < nchunks; c += 2) {
+            if (c + 1 < nchunks) omega_group<BN, kKC, 1>(t, om, 1, c + 1, nchunks, w, kb);
+            compute(a0, 0);
+            load_a(a0, c + 2);
+            lds_barrier_m();
+            if (c + 1 < nchunks) {
+                if (c + 2 < nchunks) omega_group<BN, kKC, 1>(t, om, 0, c + 2, nchunks, w, kb);
+                compute(a1, 1);
+                load_a(a1, c + 3);
+                lds_barrier_m();
+            }
+        }
+    } else {
+        // group u of kG chunks sits in slots (u & 1) kG ..; the next group is generated
+        // into the other half while this one is consumed, one barrier per group
+        for (int cb = 0; cb < nchunks; cb += kG) {
+            const int half = (cb / kG) & 1;
+            if (cb + kG < nchunks) omega_group<BN, kKC, kG>(t, om, (half ^ 1) * kG, cb + kG, nchunks, w, kb);
+#pragma unroll
+            for (int i = 0; i < kG; i += 2) {
+                if (cb + i < nchunks) {
+                    compute(a0, half * kG + i);
+                    load_a(a0, cb + i + 2);
+                }
+                if (cb + i + 1 < nchunks) {
+                    compute(a1, half * kG + i + 1);
+                    load_a(a1, cb + i + 3);
+                }
+            }
+            lds_barrier_m();
+        }
+    }
+    if (!active) return;
+
+    // ---- lane l holds Y^T rows (sketch columns) 4g .. 4g + 3 of column j of each
+    // accumulator tile: Y[rl + q][n_base + 16 nt + 4g + r] = acc[q][nt][r] ---------------
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t row = rl + q;
+        if (row >= a.m) continue;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int cn = nt * 16 + 4 * g + r;
+                if (cn >= kb) continue;
+                const int64_t col = t.n_base + cn;
+                const float v = acc[q][nt][r];
+                if (a.S == 1) {
+                    const int64_t off = a.y_trans ? col * a.ldy + row : row * a.ldy + col;
+                    double y = (double)v;
+                    if (a.y_f64) {
+                        double* Yp = static_cast<double*>(a.Y) + off;
+                        if (a.beta) y += *Yp;
+                        *Yp = y;
+                    } else {
+                        float* Yp = static_cast<float*>(a.Y) + off;
+                        if (a.beta) y += (double)*Yp;
+                        *Yp = (float)y;
+                    }
+                } else {
+                    a.partials[((int64_t)strip * a.m + row) * a.k + col] = v;
+                }
+            }
+        }
+    }
+}
+
+template <int NT, int KC>
+hipError_t launch_cm_mfma_nt(const CmMArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL((k_gemm_cm_mfma<NT, KC>), dim3((unsigned)(8 * a.tiles8)), dim3(kThreads), 0,
+                       s, a);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -774,6 +1023,61 @@ hipError_t launch_gemm_mfma_batch(const BatchArgs& a, int nt, int grid, hipStrea
     }
     if (e != hipSuccess) return e;
     return launch_reduce_batch(a, s);
+}
+
+// Column-major A, k > 16: one pass over A for all sketch columns (strips of
+// kMfmaStrip columns, FP32 partials [S][m][k], FP64 strip sums).  N-tiles per
+// workgroup are halved while the launch has fewer tiles than compute units (a
+// few-row A, e.g. the n x p factor of the Nystrom second product, where
+// generating Omega is the work): each sketch column's sums are the same for
+// any N-tile count (the chunk width stays the one of the row-major kernel for
+// this k), only A is re-read per column block.
+hipError_t launch_gemm_cm_mfma(const CmLaunch& g) {
+    const int64_t S = (g.n + kMfmaStrip - 1) / kMfmaStrip;
+    const int64_t nrb = (g.m + kBM - 1) / kBM;
+    int nt = mfma_ntiles(g.k);
+    while (nt > 1 && S * nrb * ((g.k + 16 * nt - 1) / (16 * nt)) < device_cus()) nt /= 2;
+    const int64_t BN = 16 * nt;
+    CmMArgs a{};
+    a.A = g.A;
+    a.m = g.m;
+    a.n = g.n;
+    a.lda = g.lda;
+    a.row0 = g.row0;
+    a.key0 = (uint32_t)g.seed;
+    a.key1 = (uint32_t)(g.seed >> 32);
+    a.col0 = g.col0;
+    a.dist = g.dist;
+    a.k = g.k;
+    a.Y = g.Y;
+    a.ldy = g.ldy;
+    a.y_trans = g.y_trans;
+    a.y_f64 = g.y_f64;
+    a.beta = g.beta;
+    a.S = (int)S;
+    a.partials = a.S > 1 ? static_cast<float*>(g.workspace) : nullptr;
+    a.num_rb = (int)nrb;
+    a.tiles = (int64_t)a.S * a.num_rb * ((g.k + BN - 1) / BN);
+    a.tiles8 = (a.tiles + 7) / 8;
+    hipError_t e;
+    if (chunk_cols(mfma_ntiles(g.k)) == 32) {
+        switch (nt) {
+        case 1: e = launch_cm_mfma_nt<1, 32>(a, g.stream); break;
+        case 2: e = launch_cm_mfma_nt<2, 32>(a, g.stream); break;
+        default: e = launch_cm_mfma_nt<4, 32>(a, g.stream); break;
+        }
+    } else {
+        static_assert(chunk_cols(8) == 16, "chunk of the 8-N-tile kernel");
+        switch (nt) {
+        case 1: e = launch_cm_mfma_nt<1, 16>(a, g.stream); break;
+        case 2: e = launch_cm_mfma_nt<2, 16>(a, g.stream); break;
+        case 4: e = launch_cm_mfma_nt<4, 16>(a, g.stream); break;
+        default: e = launch_cm_mfma_nt<8, 16>(a, g.stream); break;
+        }
+    }
+    if (e != hipSuccess || a.S == 1) return e;
+    return launch_reduce_partials_t(a.partials, a.S, g.m, g.k, g.Y, g.y_f64, g.ldy, g.beta,
+                                    g.y_trans, g.stream);
 }
 
 int lp_ntiles(int64_t k) { return k <= 16 ? 1 : k <= 32 ? 2 : 4; }

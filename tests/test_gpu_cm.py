@@ -1,10 +1,13 @@
 """GPU parity of column-major A (the paper's storage order), the transposed form
 Omega^T A^T, and Alg. 2's second product C = Omega^T B.
 
-Column-major kernel: each lane sums its own rows over a quarter of a strip's
-columns (<= 256 FP32 products), the four waves' sums are added in order, strips
-are summed in FP64: element bound (256 + 4) u sum |a w| + u |y|, u = 2^-24, and
-relative Frobenius <= 1e-5 against the FP64 oracle.
+Column-major kernel (k <= 16): each lane sums its own rows over a quarter of a
+strip's columns (<= 256 FP32 products), the four waves' sums are added in order,
+strips are summed in FP64: element bound (256 + 4) u sum |a w| + u |y|, u = 2^-24.
+Matrix-core kernel (k > 16): FP32 chains over 2048-column strips, bound
+(2048 + 4) u sum |a w| + u |y|; it forms the row-major matrix-core kernel's sums
+in the same order, so its result equals that of the row-major call bit for bit.
+Both: relative Frobenius <= 1e-5 against the FP64 oracle.
 """
 import numpy as np
 import pytest
@@ -29,11 +32,15 @@ def cm_dev(A, pad=0):
     return buf[:, :m].t()                       # m x n, stride (1, ld)
 
 
+def chain(k):
+    return 260 if k <= 16 else 2052
+
+
 def check(Y, A, seed, row0, col0, k, dist="normal"):
     ref = oracle.gen_matmul(A, seed, row0, col0, k, dist)
     Om = oracle.omega_block(seed, row0, A.shape[1], col0, k, dist)
     mag = oracle.matmul(np.abs(A).astype(np.float32), np.abs(Om))
-    assert (np.abs(Y - ref) <= 260 * U * mag + U * np.abs(ref)).all()
+    assert (np.abs(Y - ref) <= chain(k) * U * mag + U * np.abs(ref)).all()
     assert oracle.rel_fro(Y, ref) <= 1e-5
 
 
@@ -42,8 +49,13 @@ def check(Y, A, seed, row0, col0, k, dist="normal"):
     (1000, 1025, 16, 3, 2, 4),    # two strips of 512, padded columns
     (257, 777, 3, 1, 0, 0),       # one row past a 256-row tile, one strip
     (5, 9000, 5, 0, 0, 0),        # few rows (second-product shape)
-    (130, 3000, 20, 7, 1, 0),     # two column groups
+    (130, 3000, 20, 7, 1, 0),     # matrix cores: two 2048 strips, 20 of 32 sketch columns
     (70, 2100, 64, 0, 3, 8),
+    (1000, 5000, 64, 5, 0, 0),    # three strips (last 904), rows 512 + 488
+    (513, 2049, 17, 2, 9, 4),     # one row past a 512-row tile, one column past a strip
+    (600, 4100, 40, 0, 0, 0),     # 40 of 64 sketch columns, ragged chunk (4100 = 2*2048 + 4)
+    (3, 5000, 100, 1, 0, 0),      # three rows (one active wave), two 64-column blocks
+    (300, 2500, 256, 0, 0, 0),    # two 128-column blocks of 8 N-tiles
 ])
 def test_column_major_products(m, n, k, row0, col0, pad):
     A = normal_matrix(m, n, seed=m + n + k)
@@ -54,10 +66,37 @@ def test_column_major_products(m, n, k, row0, col0, pad):
     assert torch.equal(Yt.t(), Y)                # the transposed form holds the same bits
 
 
+@pytest.mark.parametrize("m,n,k", [(1000, 5000, 64), (513, 2049, 17), (300, 4100, 130)])
+def test_column_major_matrix_cores_equal_row_major(m, n, k):
+    """Same products in the same order as the row-major matrix-core call: equal bits."""
+    A = normal_matrix(m, n, seed=m + k)
+    Y = sk.sketch_gen_matmul_cm(cm_dev(A), 3, k, omega_row0=4)
+    ld = (n + 3) // 4 * 4                        # row-major copy, rows 16-byte aligned
+    Ar = torch.zeros((m, ld), device=DEV)
+    Ar[:, :n] = torch.from_numpy(A).to(DEV)
+    Yr = sk.sketch_gen_matmul(Ar[:, :n], 3, k, omega_row0=4)
+    assert torch.equal(Y, Yr)
+
+
+@pytest.mark.parametrize("k", [40, 130])
+def test_matrix_core_column_blocks_do_not_change_sums(k):
+    """The sketch columns per workgroup adapt to the launch (a few-row A gets one
+    16-column block per workgroup, a tall A up to 64 or 128); each column's sums are the
+    same, so rows of a tall call equal a short call bit for bit."""
+    from sketch_inputs import normal_matrix_device
+
+    m, n = 65536, 2100
+    Acm = normal_matrix_device(n, m, seed=11, device=DEV).t()    # column-major, lda = m
+    Y = sk.sketch_gen_matmul_cm(Acm, 5, k)
+    assert torch.equal(Y[:64], sk.sketch_gen_matmul_cm(Acm[:64], 5, k))
+    assert torch.equal(Y[-700:], sk.sketch_gen_matmul_cm(Acm[-700:], 5, k))
+
+
 def test_column_major_special_cases_and_options():
     n = 600
-    Y = sk.sketch_gen_matmul_cm(torch.eye(n, device=DEV).t(), 4, 9, omega_row0=5).cpu().numpy()
-    assert np.array_equal(Y.view(np.uint32), oracle.omega_block(4, 5, n, 0, 9).view(np.uint32))
+    for k in (9, 40):                            # VALU and matrix-core kernels: I * Omega = Omega
+        Y = sk.sketch_gen_matmul_cm(torch.eye(n, device=DEV).t(), 4, k, omega_row0=5).cpu().numpy()
+        assert np.array_equal(Y.view(np.uint32), oracle.omega_block(4, 5, n, 0, k).view(np.uint32))
     A = normal_matrix(200, 3000, seed=3)
     Ad = cm_dev(A)
     Y0 = torch.randn((200, 5), dtype=torch.float64, device=DEV)
@@ -68,9 +107,10 @@ def test_column_major_special_cases_and_options():
         Yd = sk.sketch_gen_matmul_cm(Ad, 2, 5, dist=dist).double().cpu().numpy()
         check(Yd, A, 2, 0, 0, 5, dist)
     # deterministic, and row blocks equal the rows of the whole
-    Yw = sk.sketch_gen_matmul_cm(Ad, 2, 5)
-    assert torch.equal(Yw, sk.sketch_gen_matmul_cm(Ad, 2, 5))
-    assert torch.equal(Yw[:100], sk.sketch_gen_matmul_cm(Ad[:100], 2, 5))
+    for k in (5, 40):
+        Yw = sk.sketch_gen_matmul_cm(Ad, 2, k)
+        assert torch.equal(Yw, sk.sketch_gen_matmul_cm(Ad, 2, k))
+        assert torch.equal(Yw[:100], sk.sketch_gen_matmul_cm(Ad[:100], 2, k))
 
 
 @pytest.mark.parametrize("n,p,k,row0", [(9000, 5, 5, 0), (5000, 64, 64, 3), (1500, 16, 20, 1)])
