@@ -189,7 +189,10 @@ int sketch_gen_matmul_reduce_dist(const void* const* A_b, int64_t P, int a_dtype
  *           of the product (Sec. 4.1 transposition remark).
  *   Other arguments as for sketch_gen_matmul_dist; workspace:
  *   sketch_workspace_size(2, SK_A_F32, m, n, k, 1).  The FP32 sums run over
- *   strips of columns with FP64 strip sums, as in the row-major calls.
+ *   strips of columns with FP64 strip sums, as in the row-major calls; for
+ *   k > 16 (matrix cores) they are the row-major call's sums in the same order,
+ *   so Y equals sketch_gen_matmul's result on the row-major copy of A bit for
+ *   bit, and a row's result does not depend on m.
  */
 int sketch_gen_matmul_cm(const float* A, int64_t m, int64_t n, int64_t lda, uint64_t seed,
                          int dist, int64_t omega_row0, int64_t omega_col0, int64_t k, void* Y,
