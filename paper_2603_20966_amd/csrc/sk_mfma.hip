@@ -11,8 +11,7 @@
 // waves share each generated Omega chunk, which halves the generation work per
 // A element against four (measured: 109 vs 75 TFLOP/s at k = 256).
 //
-// Contraction in chunks of KC columns (32, or 16 when NT = 8 fills the
-// registers):
+// Contraction in chunks of KC = 32 columns:
 //   * A goes straight from HBM into the MFMA A-operand layout: lane (g, i)
 //     (g = lane/16, i = lane%16) loads the KC/4 contiguous floats
 //     A[row i][kc + g*KC/4 ...] of each M-tile as KC/16 back-to-back 16-byte
@@ -48,8 +47,14 @@ constexpr int kWaves = 8;               // waves per workgroup
 constexpr int kThreads = 64 * kWaves;
 constexpr int kBM = kWaves * kTM * 16;  // rows per workgroup
 static_assert(kBM == kMfmaRows, "tile rows");
-// contraction columns per chunk, and floats per LDS column (chunk + 4 pad)
-constexpr int chunk_cols(int nt) { return nt >= 8 ? 16 : 32; }
+// contraction columns per chunk, and floats per LDS column (chunk + 4 pad):
+// 32 at every N-tile count, so a chunk takes 128 bytes of each row (with 16
+// columns every 128-byte line of A was fetched twice: 16 GiB instead of 8 for
+// a two-block k = 256 sketch of 32768^2, rocprofv3 FETCH_SIZE).  With 8
+// N-tiles the A operands are single-buffered (the accumulators take 128
+// registers): a chunk's 256 MFMAs cover the next chunk's load.
+constexpr int chunk_cols(int) { return 32; }
+constexpr bool single_a(int nt) { return nt >= 8; }
 constexpr int lds_row(int nt) { return chunk_cols(nt) + 4; }
 
 struct MArgs {
@@ -287,21 +292,18 @@ __device__ __forceinline__ void mfma_tile(const MTile& t, float (*om)[16 * NT][l
 
     v4f a0[kTM][kLV], a1[kTM][kLV];
     load_a(a0, 0);
-    load_a(a1, 1);
+    if constexpr (!single_a(NT)) load_a(a1, 1);
     make_chunk(0);
     lds_barrier_m();
 
     auto compute = [&](v4f (*a)[kLV], int c) {
         const int buf = c & 1;
-        v4f bop[NT][kLV];
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt)
+        for (int v = 0; v < kLV; ++v) {
+            v4f bop[NT];   // Omega operands of load v, read as they are used
 #pragma unroll
-            for (int v = 0; v < kLV; ++v)
-                bop[nt][v] =
-                    *reinterpret_cast<const v4f*>(&om[buf][nt * 16 + i16][4 * kLV * g + 4 * v]);
-#pragma unroll
-        for (int v = 0; v < kLV; ++v)
+            for (int nt = 0; nt < NT; ++nt)
+                bop[nt] = *reinterpret_cast<const v4f*>(&om[buf][nt * 16 + i16][4 * kLV * g + 4 * v]);
 #pragma unroll
             for (int s = 0; s < 4; ++s)
 #pragma unroll
@@ -309,19 +311,29 @@ __device__ __forceinline__ void mfma_tile(const MTile& t, float (*om)[16 * NT][l
 #pragma unroll
                     for (int nt = 0; nt < NT; ++nt)
                         acc[tm][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                            a[tm][v][s], bop[nt][v][s], acc[tm][nt], 0, 0, 0);
+                            a[tm][v][s], bop[nt][s], acc[tm][nt], 0, 0, 0);
+        }
     };
 
-    for (int c = 0; c < nchunks; c += 2) {
-        if (c + 1 < nchunks) make_chunk(c + 1);
-        compute(a0, c);
-        load_a(a0, c + 2);
-        lds_barrier_m();
-        if (c + 1 < nchunks) {
-            if (c + 2 < nchunks) make_chunk(c + 2);
-            compute(a1, c + 1);
-            load_a(a1, c + 3);
+    if constexpr (single_a(NT)) {
+        for (int c = 0; c < nchunks; ++c) {
+            if (c + 1 < nchunks) make_chunk(c + 1);
+            compute(a0, c);
+            load_a(a0, c + 1);
             lds_barrier_m();
+        }
+    } else {
+        for (int c = 0; c < nchunks; c += 2) {
+            if (c + 1 < nchunks) make_chunk(c + 1);
+            compute(a0, c);
+            load_a(a0, c + 2);
+            lds_barrier_m();
+            if (c + 1 < nchunks) {
+                if (c + 2 < nchunks) make_chunk(c + 2);
+                compute(a1, c + 1);
+                load_a(a1, c + 3);
+                lds_barrier_m();
+            }
         }
     }
 
@@ -512,7 +524,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm_cm_mfma(const CmMArgs a) {
 
     v4f a0[kNS], a1[kNS];
     load_a(a0, 0);
-    load_a(a1, 1);
+    if constexpr (!single_a(NT)) load_a(a1, 1);
     omega_group<BN, kKC, kG>(t, om, 0, 0, nchunks, w, kb);
     lds_barrier_m();
 
@@ -536,7 +548,14 @@ __global__ __launch_bounds__(kThreads) void k_gemm_cm_mfma(const CmMArgs a) {
                             wop[nt][v][s], x[4 * v + s][q], acc[q][nt], 0, 0, 0);
     };
 
-    if constexpr (kG == 1) {
+    if constexpr (single_a(NT)) {
+        for (int c = 0; c < nchunks; ++c) {
+            if (c + 1 < nchunks) omega_group<BN, kKC, 1>(t, om, (c + 1) & 1, c + 1, nchunks, w, kb);
+            compute(a0, c & 1);
+            load_a(a0, c + 1);
+            lds_barrier_m();
+        }
+    } else if constexpr (kG == 1) {
         for (int c = 0; c < nchunks; c += 2) {
             if (c + 1 < nchunks) omega_group<BN, kKC, 1>(t, om, 1, c + 1, nchunks, w, kb);
             compute(a0, 0);
@@ -1070,20 +1089,14 @@ hipError_t launch_gemm_cm_mfma(const CmLaunch& g) {
     a.tiles = (int64_t)a.S * a.num_rb * ((g.k + BN - 1) / BN);
     a.tiles8 = (a.tiles + 7) / 8;
     hipError_t e;
-    if (chunk_cols(mfma_ntiles(g.k)) == 32) {
-        switch (nt) {
-        case 1: e = launch_cm_mfma_nt<1, 32>(a, g.stream); break;
-        case 2: e = launch_cm_mfma_nt<2, 32>(a, g.stream); break;
-        default: e = launch_cm_mfma_nt<4, 32>(a, g.stream); break;
-        }
-    } else {
-        static_assert(chunk_cols(8) == 16, "chunk of the 8-N-tile kernel");
-        switch (nt) {
-        case 1: e = launch_cm_mfma_nt<1, 16>(a, g.stream); break;
-        case 2: e = launch_cm_mfma_nt<2, 16>(a, g.stream); break;
-        case 4: e = launch_cm_mfma_nt<4, 16>(a, g.stream); break;
-        default: e = launch_cm_mfma_nt<8, 16>(a, g.stream); break;
-        }
+    constexpr int KC = chunk_cols(8);
+    static_assert(chunk_cols(1) == KC && chunk_cols(2) == KC && chunk_cols(4) == KC,
+                  "one chunk width for every N-tile count of the row-major kernel");
+    switch (nt) {
+    case 1: e = launch_cm_mfma_nt<1, KC>(a, g.stream); break;
+    case 2: e = launch_cm_mfma_nt<2, KC>(a, g.stream); break;
+    case 4: e = launch_cm_mfma_nt<4, KC>(a, g.stream); break;
+    default: e = launch_cm_mfma_nt<8, KC>(a, g.stream); break;
     }
     if (e != hipSuccess || a.S == 1) return e;
     return launch_reduce_partials_t(a.partials, a.S, g.m, g.k, g.Y, g.y_f64, g.ldy, g.beta,
