@@ -190,11 +190,11 @@ def test_workspace_size_rules():
     assert b >= (32 + 8) * 32768 * 5 * 4                # bound valid for any 8-way split
     assert ws(2, F32, 1, 1, 1, 1) == 0 and ws(0, 5, 1, 1, 1, 1) == 0 and ws(1, F32, 1, 1, 1, 0) == 0
     assert ws(0, F32, 100, 5000, 300, 1) == 0           # k > 256 is invalid
-    # a wider VALU sketch uses narrower strips; the matrix-core path (FP32, k > 16)
-    # uses 2048-column strips
-    assert ws(0, F32, 4096, 32768, 16, 1) == 64 * 4096 * 16 * 4
+    # FP32 on the VALU path (k <= 16): 1024-column strips at every k; the matrix-core
+    # path (FP32, k > 16) uses 2048-column strips
+    assert ws(0, F32, 4096, 32768, 16, 1) == 32 * 4096 * 16 * 4
     assert ws(0, F32, 4096, 32768, 17, 1) == 16 * 4096 * 17 * 4
-    assert sk.sketch_strip_width(F32, 5) == 1024 and sk.sketch_strip_width(F32, 9) == 512
+    assert sk.sketch_strip_width(F32, 5) == 1024 and sk.sketch_strip_width(F32, 9) == 1024
     assert sk.sketch_strip_width(F32, 17) == 2048
     # FP8 at every k and BF16 past 16 columns: BF16 matrix cores, 4096-column strips
     assert sk.sketch_strip_width(BF16, 5) == 2048 and sk.sketch_strip_width(FP8, 4) == 4096
