@@ -125,8 +125,10 @@ size_t gemm_workspace_bytes(int64_t m, int64_t strips, int64_t k);
 
 // Column-major A (element (i, j) at A + j*lda + i), FP32, generated Omega; Y
 // row-major or transposed (element (i, c) at Y + c*ldy + i).  Strips of
-// cm_strip_width(kclass) columns; partials [S][m][k] as for the other kernels.
-constexpr int cm_strip_width(int kclass) { return kclass <= 8 ? 1024 : 512; }
+// cm_strip_width(kclass) columns (1024 at every k <= 16: with 512 at k = 9 ..
+// 16 the doubled partial sums cost 8-10% on 32768^2); partials [S][m][k] as
+// for the other kernels.
+constexpr int cm_strip_width(int) { return 1024; }
 struct CmLaunch {
     const float* A;
     int64_t m, n, lda, row0;

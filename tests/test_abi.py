@@ -178,7 +178,7 @@ def test_column_major_and_second_product_reject_on_host():
     ws = sk.sketch_workspace_size
     assert ws(2, F32, 300, 5000, 5, 1) == 5 * 300 * 5 * 4        # 5 strips of 1024 columns
     assert ws(2, F32, 300, 1024, 5, 1) == 0 and ws(2, BF16, 300, 5000, 5, 1) == 0
-    assert ws(2, F32, 300, 5000, 16, 1) == 10 * 300 * 16 * 4     # 512-column strips for k > 8
+    assert ws(2, F32, 300, 5000, 16, 1) == 5 * 300 * 16 * 4      # 1024-column strips at every k <= 16
 
 
 def test_workspace_size_rules():
@@ -199,10 +199,10 @@ def test_workspace_size_rules():
     # FP8 at every k and BF16 past 16 columns: BF16 matrix cores, 4096-column strips
     assert sk.sketch_strip_width(BF16, 5) == 2048 and sk.sketch_strip_width(FP8, 4) == 4096
     assert sk.sketch_strip_width(BF16, 17) == 4096 and sk.sketch_strip_width(FP8, 256) == 4096
-    # column-major A (op 2): 1024 / 512-column strips on the VALU path (k <= 16), the
+    # column-major A (op 2): 1024-column strips on the VALU path (k <= 16), the
     # matrix-core strips of 2048 columns past 16, as the row-major matrix-core call
     assert ws(2, F32, 300, 5000, 5, 1) == 5 * 300 * 5 * 4
-    assert ws(2, F32, 300, 5000, 16, 1) == 10 * 300 * 16 * 4
+    assert ws(2, F32, 300, 5000, 16, 1) == 5 * 300 * 16 * 4
     assert ws(2, F32, 300, 5000, 17, 1) == 3 * 300 * 17 * 4
     assert ws(2, F32, 64, 2048, 64, 1) == 0               # one 2048 strip: Y written directly
     assert ws(2, F32, 64, 32768, 256, 1) == 16 * 64 * 256 * 4
