@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define SKETCH_ABI_VERSION 3
+#define SKETCH_ABI_VERSION 4
 
 enum sk_status {
     SK_OK = 0,
@@ -125,7 +125,7 @@ size_t sketch_workspace_size(int op, int a_dtype, int64_t m, int64_t n, int64_t 
  *   seed       the shared seed of the global Omega.
  *   omega_row0 global row of Omega matching column 0 of A (0 <= row0, row0+n <= 2^62).
  *   omega_col0 global column of Omega matching column 0 of Y (col0+k <= 2^32).
- *   k          sketch width, 1 <= k <= 256.
+ *   k          sketch width, 1 <= k <= 1024.
  *   Y          device, m x k, storage y_dtype, leading dim ldy >= k.
  *   beta       0: Y = A*Omega;  1: Y = Y + A*Omega (old Y added in FP64).
  *   workspace  device, >= sketch_workspace_size(0, a_dtype, m, n, k, 1) bytes,
@@ -147,7 +147,7 @@ int sketch_gen_matmul_dist(const void* A, int a_dtype, int64_t m, int64_t n, int
 /*
  * Contraction split with on-device reduction (Alg. 1 on a (1, P, 1) grid: the
  * local products of P column blocks followed by the sum that Reduce-Scatter /
- * AllReduce performs across processes, Sec. 4.3 and Sec. 6.5), done in one
+ * AllReduce performs across processes, Sec. 4.3 and Sec. 6.6), done in one
  * launch on one device:
  *
  *   Y (=|+=) sum_{b=0}^{P-1} A_b[0:m, 0:n_b] * Omega(seed)[row0_b : row0_b+n_b, col0 : col0+k]
@@ -177,7 +177,7 @@ int sketch_gen_matmul_reduce_dist(const void* const* A_b, int64_t P, int a_dtype
                                   size_t workspace_bytes, void* stream);
 
 /*
- * Column-major A (the paper's storage order, Sec. 6.1), FP32:
+ * Column-major A (the paper's storage order, Secs. 6.5 and 6.6), FP32:
  *
  *   Y (=|+=) A * Omega(seed, dist)[row0 : row0+n, col0 : col0+k]
  *
@@ -260,10 +260,22 @@ int sketch_philox_raw(const uint32_t* ctr, uint64_t seed, uint32_t* out, int64_t
                       void* stream);
 
 /*
+ * The generator's normal transform alone (Sec. 6.3 generator, Box-Muller step
+ * of the Omega definition above): for 0 <= i < N,
+ *   (out[2i], out[2i+1]) = (rho cos theta, rho sin theta) of the word pair
+ *   (words[2i], words[2i+1]), rho from the even word, theta from the odd one,
+ * bit for bit the values the product kernels form.  words and out are device
+ * arrays of 2N uint32 / floats, 8-byte aligned.  For exhaustive checks of the
+ * transform over all 2^23 uniforms of each word.
+ */
+int sketch_normal_raw(const uint32_t* words, float* out, int64_t N, void* stream);
+
+/*
  * Low-precision storage of A (precision form; untimed preprocessing):
  *   dst_dtype SK_A_BF16: Aq = bf16(A), round to nearest even; scales unused.
  *   dst_dtype SK_A_FP8_E4M3: for each 128-row block b, s_b = the smallest
- *     power of two 2^E with max|A(block)| <= 448 2^E (1 for an all-zero
+ *     power of two 2^E with max|A(block)| <= 448 2^E and E >= -149
+ *     (the smallest FP32 power of two; 1 for an all-zero
  *     block); Aq(i, j) = e4m3(A(i, j) / s_b), round to nearest even,
  *     saturating at +-448; scales[b] = s_b (ceil(m/128) floats).
  *   ldq in elements of the destination type; Aq and ldq*size 16-B aligned.

@@ -85,7 +85,7 @@ typedef struct sk_request {
     uint64_t a_seed;         /* SK_SRC_SYNTH only                                      */
     uint64_t seed;           /* Omega's seed                                           */
     int64_t omega_row0, omega_col0;
-    int64_t k;               /* 1 <= k <= 256                                          */
+    int64_t k;               /* 1 <= k <= 1024                                         */
     void* Y;                 /* device, m x k, leading dim ldy >= k                    */
     int y_dtype;             /* sk_ydtype                                              */
     int64_t ldy;

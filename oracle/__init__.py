@@ -46,6 +46,7 @@ def _load():
     u64 = ctypes.c_uint64
     lib.oracle_philox_raw.argtypes = [P, P, P, i64]
     lib.oracle_normal_pair.argtypes = [ctypes.c_uint32, ctypes.c_uint32, P, P]
+    lib.oracle_normal_pairs.argtypes = [P, P, P, P, i64]
     lib.oracle_spec_log_batch.argtypes = [P, P, i64]
     lib.oracle_spec_cossin_batch.argtypes = [P, P, P, i64]
     lib.oracle_omega_value.argtypes = [u64, i64, i64]
@@ -116,6 +117,19 @@ def normal_pair(r_even: int, r_odd: int) -> tuple[float, float]:
     zs = ctypes.c_float()
     _load().oracle_normal_pair(r_even, r_odd, ctypes.byref(zc), ctypes.byref(zs))
     return zc.value, zs.value
+
+
+def normal_pairs(r_even: np.ndarray, r_odd: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
+    """FP32 Box-Muller of word pairs, elementwise: (rho cos theta, rho sin theta) arrays."""
+    ev = np.ascontiguousarray(r_even, dtype=np.uint32).ravel()
+    od = np.ascontiguousarray(r_odd, dtype=np.uint32).ravel()
+    if ev.size != od.size:
+        raise ValueError("need as many odd words as even words")
+    zc = np.empty(ev.size, dtype=np.float32)
+    zs = np.empty(ev.size, dtype=np.float32)
+    if ev.size:
+        _load().oracle_normal_pairs(_ptr(ev), _ptr(od), _ptr(zc), _ptr(zs), ev.size)
+    return zc, zs
 
 
 def spec_log(mo: np.ndarray) -> np.ndarray:

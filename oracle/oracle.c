@@ -189,6 +189,14 @@ void oracle_normal_pair(uint32_t r_even, uint32_t r_odd, float* z_cos, float* z_
     *z_sin = rho * s;
 }
 
+/* oracle_normal_pair over N word pairs (even[i], odd[i]) -> (zc[i], zs[i]). */
+void oracle_normal_pairs(const uint32_t* r_even, const uint32_t* r_odd, float* z_cos,
+                         float* z_sin, int64_t N)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < N; ++i) oracle_normal_pair(r_even[i], r_odd[i], &z_cos[i], &z_sin[i]);
+}
+
 float oracle_omega_value_dist(uint64_t seed, int64_t row, int64_t col, int dist)
 {
     uint32_t r[4];
@@ -428,6 +436,8 @@ void oracle_quantize_fp8_rows128(const float* A, int64_t m, int64_t n, int64_t l
             double ma = frexp(amax, &ea);                 /* amax = ma 2^ea */
             /* smallest E with amax <= 448 2^E = 0.875 2^(9+E) */
             E = ea - 9 + (ma > 0.875 ? 1 : 0);
+            /* the scale is stored as FP32: its smallest power of two is 2^-149 */
+            if (E < -149) E = -149;
         }
         double s = ldexp(1.0, E);
         scales[b] = (float)s;

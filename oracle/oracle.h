@@ -44,6 +44,9 @@ float oracle_omega_value_dist(uint64_t seed, int64_t row, int64_t col, int dist)
  * (rho cos theta, rho sin theta) with u = (2 (r >> 9) + 1) 2^-24,
  * rho = sqrt(-2 ln u_even), theta = 2 pi u_odd. */
 void oracle_normal_pair(uint32_t r_even, uint32_t r_odd, float* z_cos, float* z_sin);
+/* The same over N word pairs. */
+void oracle_normal_pairs(const uint32_t* r_even, const uint32_t* r_odd, float* z_cos,
+                         float* z_sin, int64_t N);
 /* The two FP32 pieces of that step for odd integers mo in [1, 2^24),
  * u = mo 2^-24: ln u, and (cos 2 pi u, sin 2 pi u). */
 void oracle_spec_log_batch(const uint32_t* mo, float* out, int64_t N);

@@ -80,12 +80,14 @@ def lib() -> ctypes.CDLL:
         L.sketch_matmul_omega.argtypes = [P, i32, i64, i64, i64, P, P, i64, i64, P, i32, i64, i32,
                                           P, sz, P]
         L.sketch_philox_raw.argtypes = [P, u64, P, i64, P]
+        L.sketch_normal_raw.argtypes = [P, P, i64, P]
         L.sketch_quantize.argtypes = [P, i64, i64, i64, i32, P, i64, P, P]
         L.sketch_trace_events.argtypes = [P, P, P]
         for f in ("sketch_gen_matmul", "sketch_gen_matmul_reduce", "sketch_gen_matmul_dist",
                   "sketch_gen_matmul_reduce_dist", "sketch_gen_omega_dist",
                   "sketch_gen_matmul_cm", "sketch_gen_tmatmul",
                   "sketch_gen_omega", "sketch_matmul_omega", "sketch_philox_raw",
+                  "sketch_normal_raw",
                   "sketch_quantize", "sketch_trace_events"):
             getattr(L, f).restype = i32
         _lib = L
@@ -152,21 +154,30 @@ def _ptr(t) -> int | None:
 
 
 _ws_cache: dict = {}
+_ws_lock = threading.Lock()
 
 
 def workspace_for(nbytes: int, device, stream_ptr: int) -> tuple[int, int]:
     """A cached workspace of at least nbytes for (device, stream).
 
-    Calls on one stream run one after the other, so they can share it.
+    Calls on one stream run one after the other, so they can share it.  The
+    buffer is marked as used by that stream (record_stream), so that when a
+    larger one replaces it, torch's caching allocator reuses its memory only
+    after the work already enqueued there has finished.  The cache is guarded
+    by a lock: host threads may share a stream.
     """
     if nbytes == 0:
         return 0, 0
-    key = (torch.device(device).index, stream_ptr)
-    buf = _ws_cache.get(key)
-    if buf is None or buf.numel() < nbytes:
-        buf = torch.empty(max(nbytes, 1 << 20), dtype=torch.uint8, device=device)
-        _ws_cache[key] = buf
-    return int(buf.data_ptr()), int(buf.numel())
+    dev = torch.device(device)
+    key = (dev.index, stream_ptr)
+    with _ws_lock:
+        buf = _ws_cache.get(key)
+        if buf is None or buf.numel() < nbytes:
+            buf = torch.empty(max(nbytes, 1 << 20), dtype=torch.uint8, device=dev)
+            if stream_ptr != torch.cuda.current_stream(dev).cuda_stream:
+                buf.record_stream(torch.cuda.ExternalStream(stream_ptr, device=dev))
+            _ws_cache[key] = buf
+        return int(buf.data_ptr()), int(buf.numel())
 
 
 # ----------------------------------------------------------------------------
@@ -348,6 +359,19 @@ def sketch_philox_raw(ctr: torch.Tensor, seed: int, *, out: torch.Tensor | None 
     return out
 
 
+def sketch_normal_raw(words: torch.Tensor, *, out: torch.Tensor | None = None,
+                      stream=None) -> torch.Tensor:
+    """The generator's FP32 Box-Muller pair of each row of words (N x 2 int32/uint32
+    device tensor: even word, odd word) -> N x 2 float32 (rho cos, rho sin)."""
+    if words.dim() != 2 or words.shape[1] != 2 or not words.is_contiguous():
+        raise ValueError("words must be a contiguous N x 2 tensor")
+    if out is None:
+        out = torch.empty(words.shape, dtype=torch.float32, device=words.device)
+    _check(lib().sketch_normal_raw(_ptr(words), _ptr(out), words.shape[0],
+                                   _stream(stream, words.device)), "sketch_normal_raw")
+    return out
+
+
 def sketch_trace_events(ev_begin, ev_mid, ev_end) -> None:
     """Arm per-phase HIP events (raw hipEvent_t handles) for this thread's next product call."""
     _check(lib().sketch_trace_events(ev_begin, ev_mid, ev_end), "sketch_trace_events")
@@ -382,5 +406,6 @@ __all__ = ["sketch_abi_version", "sketch_status_string", "sketch_workspace_size"
            "sketch_strip_width", "SketchServer", "make_request", "sk_request_footprint",
            "sketch_gen_matmul", "sketch_gen_matmul_reduce", "sketch_gen_matmul_cm",
            "sketch_gen_tmatmul",
-           "sketch_gen_omega", "sketch_matmul_omega", "sketch_philox_raw", "sketch_quantize",
+           "sketch_gen_omega", "sketch_matmul_omega", "sketch_philox_raw", "sketch_normal_raw",
+           "sketch_quantize",
            "sketch_trace_events", "SketchError", "lib", "LIB_PATH"]

@@ -324,6 +324,14 @@ int sketch_philox_raw(const uint32_t* ctr, uint64_t seed, uint32_t* out, int64_t
     return from_hip(sk::launch_philox_raw(ctr, seed, out, N, static_cast<hipStream_t>(stream)));
 }
 
+int sketch_normal_raw(const uint32_t* words, float* out, int64_t N, void* stream) {
+    if (N < 0) return SK_EINVAL;
+    if (N == 0) return SK_OK;
+    if (words == nullptr || out == nullptr) return SK_EINVAL;
+    if (((uintptr_t)words & 7u) != 0 || ((uintptr_t)out & 7u) != 0) return SK_EALIGN;
+    return from_hip(sk::launch_normal_raw(words, out, N, static_cast<hipStream_t>(stream)));
+}
+
 int sketch_quantize(const float* A, int64_t m, int64_t n, int64_t lda, int dst_dtype, void* Aq,
                     int64_t ldq, float* scales, void* stream) {
     if (dst_dtype != SK_A_BF16 && dst_dtype != SK_A_FP8_E4M3) return SK_EDTYPE;

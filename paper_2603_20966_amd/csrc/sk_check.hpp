@@ -12,7 +12,7 @@ namespace check {
 
 constexpr int64_t kMaxRow = (int64_t)1 << 62;
 constexpr int64_t kMaxCol = (int64_t)1 << 32;
-constexpr int64_t kMaxK = 256;
+constexpr int64_t kMaxK = 1024;
 constexpr int64_t kMaxGridY = 65535;
 
 inline int elem_size(int a_dtype) { return a_dtype == SK_A_F32 ? 4 : a_dtype == SK_A_BF16 ? 2 : 1; }

@@ -1,5 +1,5 @@
 // Column-major A: Y = A * Omega(seed) with A stored by columns (element (i, j)
-// at A + j*lda + i), the paper's storage order (Sec. 6.1), and optionally Y
+// at A + j*lda + i), the paper's storage order (Secs. 6.5 and 6.6), and optionally Y
 // stored transposed (the form Omega^T A^T of the transposition remark in
 // Sec. 4.1).  The same kernel computes Alg. 2's second product C = Omega^T B:
 // a row-major B (n x p) is B^T stored by columns, and C = (B^T Omega)^T.

@@ -10,15 +10,18 @@
 //   * the workgroup first builds its C x kg slice of Omega in LDS (generated
 //     from the seed, or copied from an explicit Omega for the stored-operand
 //     variant), so Omega never exists in HBM on the generated path;
-//   * each wave then streams 16 rows at a time: 16 lanes per row, each lane
-//     loading 16 contiguous bytes of A per step (a 256-byte coalesced row
-//     segment), multiplying by the matching Omega values from LDS with FP32
-//     FMAs into per-lane accumulators;
+//   * each wave then streams passes of 8 rows (32 rows apart between the
+//     four waves): all 64 lanes read one row segment per step, 16 contiguous
+//     bytes per lane (1 KB per load instruction), and multiply them by the
+//     matching Omega values from LDS with FP32 FMAs into per-lane
+//     accumulators (8 rows x kg columns per lane);
 //   * the first loads of A are issued before the Omega slice is generated,
-//     and each wave keeps four steps of nontemporal loads in flight across
+//     and each wave keeps two steps of nontemporal loads in flight across
 //     its passes;
-//   * the 16 lanes of a row are summed by a fixed DPP butterfly, giving the
-//     FP32 partial of (row, strip, column); partials go to the workspace;
+//   * at the end of a pass the 64 lanes' accumulators are summed by a fixed
+//     reduce-scatter (permlane32 and permlane16 swaps, then a DPP butterfly
+//     inside 16-lane rows), giving the FP32 partial of (row, strip, column);
+//     partials go to the workspace;
 //   * a second small kernel sums the partials of all strips in FP64, in strip
 //     order, adds beta * Y, rounds once and writes Y.  (No cross-workgroup
 //     synchronisation inside the streaming kernel: device-scope release /

@@ -184,6 +184,8 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_zero_matrix(void* Y, int f64, int64_t m, int64_t k, int64_t ldy, hipStream_t s);
 hipError_t launch_philox_raw(const uint32_t* ctr, uint64_t seed, uint32_t* out, int64_t N,
                              hipStream_t s);
+// out[2i], out[2i+1] = the generator's FP32 Box-Muller pair of words[2i], words[2i+1].
+hipError_t launch_normal_raw(const uint32_t* words, float* out, int64_t N, hipStream_t s);
 hipError_t launch_gen_omega(uint64_t seed, int dist, int64_t row0, int64_t n, int64_t col0,
                             int64_t k, float* Om, int64_t ldo, hipStream_t s);
 hipError_t launch_quantize(const float* A, int64_t m, int64_t n, int64_t lda, int dst, void* Aq,

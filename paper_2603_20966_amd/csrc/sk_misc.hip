@@ -17,6 +17,17 @@ __global__ void k_philox_raw(const uint4* ctr, uint32_t k0, uint32_t k1, uint4* 
     out[i] = make_uint4(r.x, r.y, r.z, r.w);
 }
 
+// The FP32 Box-Muller pair of each word pair, exactly as the generator forms
+// it inside the product kernels.
+__global__ void k_normal_raw(const uint2* words, float2* out, int64_t N) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const uint2 w = words[i];
+    float zc, zs;
+    box_muller(w.x, w.y, zc, zs);
+    out[i] = make_float2(zc, zs);
+}
+
 // One thread per (Philox counter q, column c): writes Omega rows 4q..4q+3
 // that fall inside [row0, row0+n).
 __global__ void k_gen_omega(uint32_t k0, uint32_t k1, int dist, int64_t row0, int64_t n,
@@ -78,9 +89,13 @@ __global__ void k_zero(uint32_t* p, int64_t words) {
         p[i] = 0u;
 }
 
+// Y[0:m, 0:k] = 0 with leading dimension ldy: a grid-stride loop over the m*k
+// elements, so any m fits the one-dimensional grid.
 __global__ void k_zero_matrix(void* Y, int f64, int64_t m, int64_t k, int64_t ldy) {
-    const int64_t i = blockIdx.y;
-    for (int64_t c = threadIdx.x; c < k; c += blockDim.x) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m * k;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / k;
+        const int64_t c = e - i * k;
         if (f64) static_cast<double*>(Y)[i * ldy + c] = 0.0;
         else static_cast<float*>(Y)[i * ldy + c] = 0.0f;
     }
@@ -125,7 +140,9 @@ __global__ void k_amax_rows128(const float* A, int64_t m, int64_t n, int64_t lda
         atomicMax(&amax[b], max(max(wmax[0], wmax[1]), max(wmax[2], wmax[3])));
 }
 
-// amax bits -> power-of-two scale 2^E, the smallest with amax <= 448 * 2^E.
+// amax bits -> power-of-two scale 2^E, the smallest with amax <= 448 * 2^E
+// among the powers of two an FP32 scale can hold (E >= -149, the smallest
+// subnormal: a block whose amax is at most 448 * 2^-149 gets 2^-149).
 __global__ void k_fp8_scales(uint32_t* s, int64_t nb) {
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= nb) return;
@@ -133,8 +150,8 @@ __global__ void k_fp8_scales(uint32_t* s, int64_t nb) {
     float scale = 1.0f;
     if (bits != 0u) {
         const float amax = __uint_as_float(bits);
-        int E = -150;
-        // 448 * 2^E grows by 2x per step; start below any FP32 value
+        int E = -149;
+        // 448 * 2^E (exact for E >= -149) doubles per step
         float lim = __builtin_ldexpf(448.0f, E);
         while (lim < amax) {
             ++E;
@@ -169,13 +186,24 @@ __device__ __forceinline__ uint8_t e4m3_code(float x) {
     return (uint8_t)(sign | code);
 }
 
+// Exponent E of a power-of-two scale 2^E, -149 <= E <= 127, read from its bits
+// (normal: the biased exponent; subnormal: the position of its one set bit).
+__device__ __forceinline__ int pow2_exponent(float s) {
+    const uint32_t u = __float_as_uint(s);
+    if (u >= 0x00800000u) return (int)(u >> 23) - 127;
+    return (31 - __clz(u)) - 149;
+}
+
+// A / s_b as x * 2^-E: exact (the quotient is at most 448 in magnitude, and a
+// result below FP32's normal range lies far under FP8's smallest step), with no
+// reciprocal that could overflow for E <= -128.
 __global__ void k_to_fp8(const float* A, int64_t m, int64_t n, int64_t lda, const float* scales,
                          uint8_t* Q, int64_t ldq) {
     const int64_t i = blockIdx.y;
-    const float inv = 1.0f / scales[i >> 7];   // exact: scales are powers of two
+    const int negE = -pow2_exponent(scales[i >> 7]);
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
          j += (int64_t)gridDim.x * blockDim.x)
-        Q[i * ldq + j] = e4m3_code(A[i * lda + j] * inv);
+        Q[i * ldq + j] = e4m3_code(__builtin_ldexpf(A[i * lda + j], negE));
 }
 
 }  // namespace
@@ -198,7 +226,8 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
 hipError_t launch_zero_matrix(void* Y, int f64, int64_t m, int64_t k, int64_t ldy,
                               hipStream_t s) {
     if (m == 0 || k == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_zero_matrix, dim3(1, (unsigned)m), dim3(64), 0, s, Y, f64, m, k, ldy);
+    const int64_t blocks = std::min<int64_t>((m * k + 255) / 256, 16384);
+    hipLaunchKernelGGL(k_zero_matrix, dim3((unsigned)blocks), dim3(256), 0, s, Y, f64, m, k, ldy);
     return hipGetLastError();
 }
 
@@ -208,6 +237,13 @@ hipError_t launch_philox_raw(const uint32_t* ctr, uint64_t seed, uint32_t* out, 
     hipLaunchKernelGGL(k_philox_raw, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s,
                        reinterpret_cast<const uint4*>(ctr), (uint32_t)seed,
                        (uint32_t)(seed >> 32), reinterpret_cast<uint4*>(out), N);
+    return hipGetLastError();
+}
+
+hipError_t launch_normal_raw(const uint32_t* words, float* out, int64_t N, hipStream_t s) {
+    if (N == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_normal_raw, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s,
+                       reinterpret_cast<const uint2*>(words), reinterpret_cast<float2*>(out), N);
     return hipGetLastError();
 }
 

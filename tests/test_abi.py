@@ -48,7 +48,7 @@ def test_header_symbols_exported():
 
 
 def test_version_and_status_strings():
-    assert sk.sketch_abi_version() == 3
+    assert sk.sketch_abi_version() == 4
     for st in range(-10, 1):
         assert sk.sketch_status_string(st) != "unknown status"
     assert sk.sketch_status_string(-100) == "unknown status"
@@ -62,7 +62,7 @@ def gm(A=PA, adt=F32, m=64, n=1024, lda=1024, scales=None, seed=1, row0=0, col0=
 
 @pytest.mark.parametrize("kw,expect", [
     (dict(adt=3), EDTYPE), (dict(adt=-1), EDTYPE), (dict(ydt=2), EDTYPE),
-    (dict(m=-1), EINVAL), (dict(n=-1), EINVAL), (dict(k=-1), EINVAL), (dict(k=257), EINVAL),
+    (dict(m=-1), EINVAL), (dict(n=-1), EINVAL), (dict(k=-1), EINVAL), (dict(k=1025), EINVAL),
     (dict(beta=2), EINVAL), (dict(Y=None), EINVAL), (dict(ldy=4), EINVAL),
     (dict(A=None), EINVAL), (dict(lda=1000), EINVAL), (dict(row0=-1), EINVAL),
     (dict(row0=(1 << 62) - 100), EINVAL), (dict(col0=-1), EINVAL),
@@ -165,7 +165,7 @@ def test_column_major_and_second_product_reject_on_host():
     assert cm(lda=302) == EALIGN                 # lda * 4 not a multiple of 16
     assert cm(A=PA + 4) == EALIGN
     assert cm(dist=5) == EINVAL and cm(yt=2) == EINVAL and cm(beta=3) == EINVAL
-    assert cm(k=257, ldy=300) == EINVAL
+    assert cm(k=1025, ldy=1100) == EINVAL
     assert cm(ldy=4) == EINVAL                   # row-major Y needs ldy >= k
     assert cm(yt=1, ldy=299) == EINVAL           # transposed Y needs ldy >= m
     assert cm(ydt=3) == EDTYPE
@@ -189,7 +189,8 @@ def test_workspace_size_rules():
     b = ws(1, F32, 32768, 32768, 5, 8)
     assert b >= (32 + 8) * 32768 * 5 * 4                # bound valid for any 8-way split
     assert ws(2, F32, 1, 1, 1, 1) == 0 and ws(0, 5, 1, 1, 1, 1) == 0 and ws(1, F32, 1, 1, 1, 0) == 0
-    assert ws(0, F32, 100, 5000, 300, 1) == 0           # k > 256 is invalid
+    assert ws(0, F32, 100, 5000, 1025, 1) == 0          # k > 1024 is invalid
+    assert ws(0, F32, 100, 5000, 1024, 1) == 3 * 100 * 1024 * 4   # 2048-column strips
     # FP32 on the VALU path (k <= 16): 1024-column strips at every k; the matrix-core
     # path (FP32, k > 16) uses 2048-column strips
     assert ws(0, F32, 4096, 32768, 16, 1) == 32 * 4096 * 16 * 4

@@ -53,6 +53,23 @@ def test_fp8_codes_and_scales_bit_exact(m, n):
     assert np.array_equal(Aq.cpu().numpy(), Q)
 
 
+def test_fp8_tiny_huge_and_subnormal_blocks_bit_exact():
+    """Scales far from 1: a block near FP32's smallest normal (scale 2^-133, whose
+    reciprocal is not an FP32 number), a block of FP32 subnormals only (scale at
+    the FP32 floor 2^-149), a block near 1e30, and an ordinary block."""
+    A = normal_matrix(512, 300, seed=4)
+    A[0:128] *= np.float32(1e-38)
+    A[128:256] *= np.float32(1e-43)
+    A[256:384] *= np.float32(1e30)
+    assert 0 < np.abs(A[128:256]).max() < np.float32(2.0 ** -126)
+    Aq, sc = sk.sketch_quantize(dev_f32(A), "fp8")
+    Q, s = oracle.quantize_fp8_rows128(A)
+    assert s[1] == np.float32(2.0 ** -149) and s[0] < np.float32(2.0 ** -126)
+    assert np.array_equal(sc.cpu().numpy().view(np.uint32), s.view(np.uint32))
+    assert np.array_equal(Aq.cpu().numpy(), Q)
+    assert Q[0:128].any() and Q[128:256].any()
+
+
 def test_fp8_zero_block_scale_is_one():
     A = np.zeros((200, 64), dtype=np.float32)
     A[:128] = normal_matrix(128, 64, seed=1)

@@ -10,6 +10,7 @@
 """
 import time
 
+import numpy as np
 import pytest
 import torch
 
@@ -80,6 +81,41 @@ def test_alone_mix_and_direct_bitwise():
         m, n, k, r0, c0 = MIX[q]
         ref = oracle.gen_matmul(As[q][0], 100 + k, r0, c0, k)
         assert oracle.rel_fro(Ym[q].double().cpu().numpy(), ref) <= 1e-5
+
+
+def test_sixty_served_requests_against_oracle():
+    """60 requests of the serving workload's mix (Poisson arrivals, m and n
+    log-uniform, k uniform over {5, 16, 64}, distinct Omega seeds), scaled to
+    m, n in [256, 4096] so the FP64 oracle checks every element: each served Y
+    within the element bound of its kernel (80 u on the VALU path, 2052 u on the
+    matrix cores; u = 2^-24) and within 1e-5 relative Frobenius."""
+    from sketch_inputs import request_stream
+
+    U = 2.0 ** -24
+    reqs = request_stream(60, seed=7, rate_per_s=1.0, mn_lo=256, mn_hi=4096)
+    As = [dev_matrix(r["m"], r["n"], seed=r["seed_a"]) for r in reqs]
+    Ys = [torch.full((r["m"], r["k"]), float("nan"), device=DEV) for r in reqs]
+    torch.cuda.synchronize()
+    with sk.SketchServer(1 << 30, max_slots=16, max_batch=16) as srv:
+        ts = [srv.submit(sv.make_request(A=Ad, k=r["k"], seed=r["seed_omega"], Y=Y,
+                                         omega_row0=r["id"] % 5), Ad, Y)
+              for r, (_, Ad), Y in zip(reqs, As, Ys)]
+        infos = [srv.wait(t, 60.0) for t in ts]
+        st = srv.stats()
+    assert all(i["state"] == sv.SK_REQ_DONE and i["status"] == 0 for i in infos)
+    assert st["batches"] < len(reqs)
+    classes = set()
+    for r, (A, _), Y in zip(reqs, As, Ys):
+        k, row0 = r["k"], r["id"] % 5
+        got = Y.double().cpu().numpy()
+        ref = oracle.gen_matmul(A, r["seed_omega"], row0, 0, k)
+        Om = oracle.omega_block(r["seed_omega"], row0, r["n"], 0, k)
+        mag = oracle.matmul(np.abs(A), np.abs(Om))
+        c = 80 if k <= 16 else 2052
+        assert (np.abs(got - ref) <= c * U * mag + U * np.abs(ref)).all(), r
+        assert oracle.rel_fro(got, ref) <= 1e-5, r
+        classes.add(k)
+    assert classes == {5, 16, 64}
 
 
 def test_host_and_synthetic_sources():
@@ -207,7 +243,7 @@ def test_request_validation():
     Y = torch.empty((10, 5), device=DEV)
     A = torch.empty((10, 64), device=DEV)
     with sk.SketchServer(1 << 20, max_slots=2, max_batch=2) as srv:
-        for bad in (dict(k=0), dict(k=300)):
+        for bad in (dict(k=0), dict(k=1025)):
             with pytest.raises(sk.SketchError):
                 srv.submit(sv.make_request(A=A, seed=1, Y=Y, **bad))
         r = sv.make_request(A=A, k=5, seed=1, Y=Y)

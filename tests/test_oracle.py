@@ -142,6 +142,12 @@ def test_normal_pair_matches_libm_box_muller():
                          (zs, rho * math.sin(2 * math.pi * uo))):
             tol = 5 * float(np.spacing(np.float32(abs(ref)))) + 4 * rho * 2.0 ** -24 * 2e-6
             assert abs(got - ref) <= tol, (re_, ro, got, ref)
+    # the batch form is the same function
+    w32 = words.astype(np.uint32)
+    zc, zs = oracle.normal_pairs(w32[:, 0], w32[:, 1])
+    one = np.array([oracle.normal_pair(int(a), int(b)) for a, b in w32[:500]], dtype=np.float32)
+    assert np.array_equal(zc[:500].view(np.uint32), one[:, 0].view(np.uint32))
+    assert np.array_equal(zs[:500].view(np.uint32), one[:, 1].view(np.uint32))
 
 
 def test_omega_matches_f64_reference_and_word_layout():
@@ -405,6 +411,30 @@ def test_fp8_rows128_scales_definition():
     rel = np.abs(deq - A) / np.maximum(np.abs(A), 1e-30)
     mask = np.abs(A) >= 2.0 ** -6 * np.repeat(s, 128)[:300, None]
     assert rel[mask].max() <= 2.0 ** -4 + 1e-12   # 3 mantissa bits, round to nearest
+
+
+def test_fp8_scales_at_fp32_extremes():
+    """Scales are FP32 powers of two: the smallest one with amax <= 448 s, but never
+    below 2^-149 (FP32's smallest power of two).  Codes are torch's E4M3 cast of the
+    exact quotient A / s."""
+    import torch
+
+    A = normal_matrix(512, 64, seed=17)
+    A[0:128] *= np.float32(1e-38)           # scale 2^-133: its reciprocal overflows FP32
+    A[128:256] *= np.float32(1e-43)         # subnormals only: amax < 448 * 2^-149
+    A[256:384] *= np.float32(1e30)
+    Q, s = oracle.quantize_fp8_rows128(A)
+    assert s[1] == np.float32(2.0 ** -149)
+    for b in range(4):
+        blk = A[128 * b:128 * (b + 1)].astype(np.float64)
+        amax = float(np.abs(blk).max())
+        E = math.log2(float(s[b]))
+        assert E == int(E) and E >= -149
+        assert amax <= 448 * float(s[b])
+        assert amax > 448 * float(s[b]) / 2 or E == -149
+        q = torch.from_numpy((blk / float(s[b])).astype(np.float32))
+        ref = q.to(torch.float8_e4m3fn).view(torch.uint8).numpy()
+        assert np.array_equal(Q[128 * b:128 * (b + 1)], ref)
 
 
 def test_quantized_product_equals_product_of_dequantized():
