@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define SKETCH_ABI_VERSION 4
+#define SKETCH_ABI_VERSION 5
 
 enum sk_status {
     SK_OK = 0,
@@ -64,7 +64,8 @@ enum sk_status {
     SK_EUNSUPPORTED = -7,  /* valid request this build does not handle            */
     SK_EBUDGET = -8,       /* (serving) request larger than the memory budget     */
     SK_EQUEUE = -9,        /* (serving) queue full or unknown ticket              */
-    SK_ETIMEOUT = -10      /* (serving) wait ended before the request finished    */
+    SK_ETIMEOUT = -10,     /* (serving) wait ended before the request finished    */
+    SK_ESCRATCH = -11      /* call needs more than the library's static scratch   */
 };
 
 /* Storage type of A. */
@@ -136,6 +137,28 @@ int sketch_gen_matmul(const void* A, int a_dtype, int64_t m, int64_t n, int64_t 
                       const float* a_scales, uint64_t seed, int64_t omega_row0,
                       int64_t omega_col0, int64_t k, void* Y, int y_dtype, int64_t ldy,
                       int beta, void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * sketch_gen_matmul without a workspace argument.  The strip partials go to a
+ * fixed device array inside the library, SKETCH_NOALLOC_SCRATCH_BYTES bytes
+ * per GPU, held from the first call on that GPU until the process ends; the
+ * call itself allocates nothing.  Arguments, results and errors are those of
+ * sketch_gen_matmul (same kernels, bitwise the same Y), plus SK_ESCRATCH when
+ * sketch_workspace_size(0, a_dtype, m, n, k, 1) exceeds
+ * SKETCH_NOALLOC_SCRATCH_BYTES (checked on the host, nothing enqueued).
+ * `stream` must belong to the current device.  Every call on one GPU uses
+ * the same array and leaves its contents behind (each call writes all it
+ * reads, so nothing needs clearing): calls that may overlap on one GPU --
+ * other streams, other host threads -- race and must be serialised by the
+ * caller.
+ */
+#define SKETCH_NOALLOC_SCRATCH_BYTES (32u << 20)
+int sketch_gen_matmul_noalloc(const void* A, int a_dtype, int64_t m, int64_t n, int64_t lda,
+                              const float* a_scales, uint64_t seed, int64_t omega_row0,
+                              int64_t omega_col0, int64_t k, void* Y, int y_dtype, int64_t ldy,
+                              int beta, void* stream);
 
 /* sketch_gen_matmul with Omega drawn from the distribution `dist` (sk_dist;
  * SK_EINVAL otherwise).  Results obey every rule stated for sketch_gen_matmul. */

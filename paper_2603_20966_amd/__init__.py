@@ -28,7 +28,7 @@ SK_Y_F32, SK_Y_F64 = 0, 1
 SK_DIST = {"normal": 0, "uniform": 1, "rademacher": 2}
 STATUS = {0: "SK_OK", -1: "SK_EINVAL", -2: "SK_EDTYPE", -3: "SK_EALIGN", -4: "SK_EWORKSPACE",
           -5: "SK_EHIP", -6: "SK_ENOMEM", -7: "SK_EUNSUPPORTED", -8: "SK_EBUDGET",
-          -9: "SK_EQUEUE", -10: "SK_ETIMEOUT"}
+          -9: "SK_EQUEUE", -10: "SK_ETIMEOUT", -11: "SK_ESCRATCH"}
 
 _lib = None
 _lock = threading.Lock()
@@ -65,6 +65,8 @@ def lib() -> ctypes.CDLL:
         L.sketch_strip_width.restype = i64
         L.sketch_gen_matmul.argtypes = [P, i32, i64, i64, i64, P, u64, i64, i64, i64, P, i32, i64,
                                         i32, P, sz, P]
+        L.sketch_gen_matmul_noalloc.argtypes = [P, i32, i64, i64, i64, P, u64, i64, i64, i64, P,
+                                                i32, i64, i32, P]
         L.sketch_gen_matmul_reduce.argtypes = [P, i64, i32, i64, P, P, P, P, u64, i64, i64, P, i32,
                                                i64, i32, P, sz, P]
         L.sketch_gen_omega.argtypes = [u64, i64, i64, i64, i64, P, i64, P]
@@ -83,7 +85,7 @@ def lib() -> ctypes.CDLL:
         L.sketch_normal_raw.argtypes = [P, P, i64, P]
         L.sketch_quantize.argtypes = [P, i64, i64, i64, i32, P, i64, P, P]
         L.sketch_trace_events.argtypes = [P, P, P]
-        for f in ("sketch_gen_matmul", "sketch_gen_matmul_reduce", "sketch_gen_matmul_dist",
+        for f in ("sketch_gen_matmul", "sketch_gen_matmul_noalloc", "sketch_gen_matmul_reduce", "sketch_gen_matmul_dist",
                   "sketch_gen_matmul_reduce_dist", "sketch_gen_omega_dist",
                   "sketch_gen_matmul_cm", "sketch_gen_tmatmul",
                   "sketch_gen_omega", "sketch_matmul_omega", "sketch_philox_raw",
@@ -220,6 +222,23 @@ def sketch_gen_matmul(A: torch.Tensor, seed: int, k: int, *, omega_row0: int = 0
                                         _dist(dist), omega_row0, omega_col0, k, _ptr(Y),
                                         _ydtype(Y.dtype), ldy, beta, wsp, wsb, st),
            "sketch_gen_matmul")
+    return Y
+
+
+def sketch_gen_matmul_noalloc(A: torch.Tensor, seed: int, k: int, *, omega_row0: int = 0,
+                              omega_col0: int = 0, Y: torch.Tensor | None = None, beta: int = 0,
+                              a_scales: torch.Tensor | None = None, y_dtype=torch.float32,
+                              stream=None) -> torch.Tensor:
+    """sketch_gen_matmul with the library's static scratch instead of a workspace (no device
+    allocation inside the call; pass Y to allocate nothing here either)."""
+    m, n = A.shape
+    lda = _ld(A, "A") if m > 0 else max(n, 1)
+    Y = _out(Y, m, k, y_dtype if Y is None else Y.dtype, A.device)
+    ldy = _ld(Y, "Y") if m > 0 else max(k, 1)
+    _check(lib().sketch_gen_matmul_noalloc(_ptr(A), _adtype(A), m, n, lda, _ptr(a_scales), seed,
+                                           omega_row0, omega_col0, k, _ptr(Y), _ydtype(Y.dtype),
+                                           ldy, beta, _stream(stream, A.device)),
+           "sketch_gen_matmul_noalloc")
     return Y
 
 
@@ -404,7 +423,8 @@ from .serve import SketchServer, make_request, sk_request_footprint  # noqa: E40
 
 __all__ = ["sketch_abi_version", "sketch_status_string", "sketch_workspace_size",
            "sketch_strip_width", "SketchServer", "make_request", "sk_request_footprint",
-           "sketch_gen_matmul", "sketch_gen_matmul_reduce", "sketch_gen_matmul_cm",
+           "sketch_gen_matmul", "sketch_gen_matmul_noalloc", "sketch_gen_matmul_reduce",
+           "sketch_gen_matmul_cm",
            "sketch_gen_tmatmul",
            "sketch_gen_omega", "sketch_matmul_omega", "sketch_philox_raw", "sketch_normal_raw",
            "sketch_quantize",

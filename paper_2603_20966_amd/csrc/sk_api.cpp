@@ -72,6 +72,7 @@ const char* sketch_status_string(int status) {
     case SK_EBUDGET: return "request exceeds the memory budget";
     case SK_EQUEUE: return "queue full or unknown ticket";
     case SK_ETIMEOUT: return "wait timed out before the request finished";
+    case SK_ESCRATCH: return "call needs more workspace than the library's static scratch holds";
     default: return "unknown status";
     }
 }
@@ -101,12 +102,18 @@ int sketch_trace_events(void* ev_begin, void* ev_mid, void* ev_end) {
     return SK_OK;
 }
 
-static int gen_matmul_impl(const void* A, int a_dtype, int64_t m, int64_t n, int64_t lda,
-                           const float* a_scales, uint64_t seed, int dist, int64_t omega_row0,
-                           int64_t omega_col0, const float* Omega, int64_t ldo, int64_t k,
-                           void* Y, int y_dtype, int64_t ldy, int beta, void* workspace,
-                           size_t workspace_bytes, void* stream) {
-    const sk::TraceEvents trace = take_trace();
+}  // extern "C"
+
+namespace sk {
+
+// Host-side checks of a sketch_gen_matmul-style call (explicit Omega when
+// Omega != nullptr or ldo != 0); on success *need holds the workspace bytes
+// the call requires.  Makes no HIP call.
+int gen_matmul_validate(const void* A, int a_dtype, int64_t m, int64_t n, int64_t lda,
+                        const float* a_scales, int dist, int64_t omega_row0, int64_t omega_col0,
+                        const float* Omega, int64_t ldo, int64_t k, const void* Y, int y_dtype,
+                        int64_t ldy, int beta, size_t* need) {
+    *need = 0;
     if (!dist_ok(dist)) return SK_EINVAL;
     int st = check_common(a_dtype, m, k, omega_col0, Y, y_dtype, ldy, beta);
     if (st != SK_OK) return st;
@@ -117,8 +124,24 @@ static int gen_matmul_impl(const void* A, int a_dtype, int64_t m, int64_t n, int
         if (n > 0 && (Omega == nullptr || ldo < k)) return SK_EINVAL;
         if (((uintptr_t)Omega & 3u) != 0) return SK_EALIGN;
     }
-    st = check_workspace(n > 0 ? workspace_for(0, a_dtype, m, n, k, 1) : 0, workspace,
-                         workspace_bytes);
+    *need = n > 0 ? workspace_for(0, a_dtype, m, n, k, 1) : 0;
+    return SK_OK;
+}
+
+void drop_trace() { (void)take_trace(); }
+
+int gen_matmul_impl(const void* A, int a_dtype, int64_t m, int64_t n, int64_t lda,
+                    const float* a_scales, uint64_t seed, int dist, int64_t omega_row0,
+                    int64_t omega_col0, const float* Omega, int64_t ldo, int64_t k, void* Y,
+                    int y_dtype, int64_t ldy, int beta, void* workspace, size_t workspace_bytes,
+                    void* stream) {
+    const sk::TraceEvents trace = take_trace();
+    size_t need = 0;
+    int st = gen_matmul_validate(A, a_dtype, m, n, lda, a_scales, dist, omega_row0, omega_col0,
+                                 Omega, ldo, k, Y, y_dtype, ldy, beta, &need);
+    if (st != SK_OK) return st;
+    if (m == 0 || k == 0) return SK_OK;
+    st = check_workspace(need, workspace, workspace_bytes);
     if (st != SK_OK) return st;
     sk::GemmLaunch g{};
     g.adtype = a_dtype;
@@ -142,11 +165,15 @@ static int gen_matmul_impl(const void* A, int a_dtype, int64_t m, int64_t n, int
     return run_product(g, n);
 }
 
+}  // namespace sk
+
+extern "C" {
+
 int sketch_gen_matmul(const void* A, int a_dtype, int64_t m, int64_t n, int64_t lda,
                       const float* a_scales, uint64_t seed, int64_t omega_row0,
                       int64_t omega_col0, int64_t k, void* Y, int y_dtype, int64_t ldy,
                       int beta, void* workspace, size_t workspace_bytes, void* stream) {
-    return gen_matmul_impl(A, a_dtype, m, n, lda, a_scales, seed, SK_DIST_NORMAL, omega_row0,
+    return sk::gen_matmul_impl(A, a_dtype, m, n, lda, a_scales, seed, SK_DIST_NORMAL, omega_row0,
                            omega_col0, nullptr, 0, k, Y, y_dtype, ldy, beta, workspace,
                            workspace_bytes, stream);
 }
@@ -155,7 +182,7 @@ int sketch_gen_matmul_dist(const void* A, int a_dtype, int64_t m, int64_t n, int
                            const float* a_scales, uint64_t seed, int dist, int64_t omega_row0,
                            int64_t omega_col0, int64_t k, void* Y, int y_dtype, int64_t ldy,
                            int beta, void* workspace, size_t workspace_bytes, void* stream) {
-    return gen_matmul_impl(A, a_dtype, m, n, lda, a_scales, seed, dist, omega_row0, omega_col0,
+    return sk::gen_matmul_impl(A, a_dtype, m, n, lda, a_scales, seed, dist, omega_row0, omega_col0,
                            nullptr, 0, k, Y, y_dtype, ldy, beta, workspace, workspace_bytes,
                            stream);
 }
@@ -165,7 +192,7 @@ int sketch_matmul_omega(const void* A, int a_dtype, int64_t m, int64_t n, int64_
                         void* Y, int y_dtype, int64_t ldy, int beta, void* workspace,
                         size_t workspace_bytes, void* stream) {
     if (n > 0 && m > 0 && k > 0 && (Omega == nullptr || ldo < k)) return SK_EINVAL;
-    return gen_matmul_impl(A, a_dtype, m, n, lda, a_scales, 0, SK_DIST_NORMAL, 0, 0, Omega,
+    return sk::gen_matmul_impl(A, a_dtype, m, n, lda, a_scales, 0, SK_DIST_NORMAL, 0, 0, Omega,
                            ldo < 1 ? 1 : ldo, k, Y, y_dtype, ldy, beta, workspace,
                            workspace_bytes, stream);
 }

@@ -191,4 +191,19 @@ hipError_t launch_gen_omega(uint64_t seed, int dist, int64_t row0, int64_t n, in
 hipError_t launch_quantize(const float* A, int64_t m, int64_t n, int64_t lda, int dst, void* Aq,
                            int64_t ldq, float* scales, hipStream_t s);
 
+// The C ABI's sketch_gen_matmul path, shared by the entry points that bring
+// their own workspace and by the one that uses the library's static scratch.
+// gen_matmul_validate makes no HIP call; *need receives the workspace bytes.
+int gen_matmul_validate(const void* A, int a_dtype, int64_t m, int64_t n, int64_t lda,
+                        const float* a_scales, int dist, int64_t omega_row0, int64_t omega_col0,
+                        const float* Omega, int64_t ldo, int64_t k, const void* Y, int y_dtype,
+                        int64_t ldy, int beta, size_t* need);
+int gen_matmul_impl(const void* A, int a_dtype, int64_t m, int64_t n, int64_t lda,
+                    const float* a_scales, uint64_t seed, int dist, int64_t omega_row0,
+                    int64_t omega_col0, const float* Omega, int64_t ldo, int64_t k, void* Y,
+                    int y_dtype, int64_t ldy, int beta, void* workspace, size_t workspace_bytes,
+                    void* stream);
+// Consumes the events armed by sketch_trace_events for this thread.
+void drop_trace();
+
 }  // namespace sk

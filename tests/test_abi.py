@@ -48,8 +48,8 @@ def test_header_symbols_exported():
 
 
 def test_version_and_status_strings():
-    assert sk.sketch_abi_version() == 4
-    for st in range(-10, 1):
+    assert sk.sketch_abi_version() == 5
+    for st in range(-11, 1):
         assert sk.sketch_status_string(st) != "unknown status"
     assert sk.sketch_status_string(-100) == "unknown status"
 
@@ -79,6 +79,43 @@ def test_gen_matmul_rejects(kw, expect):
     args = dict(n=4096, lda=4096)
     args.update(kw)
     assert gm(**args) == expect
+
+
+NOALLOC_BYTES = 32 << 20    # SKETCH_NOALLOC_SCRATCH_BYTES
+
+
+def gm_noalloc(A=PA, adt=F32, m=64, n=4096, lda=4096, scales=None, seed=1, row0=0, col0=0, k=5,
+               Y=PB, ydt=YF32, ldy=5, beta=0, stream=None):
+    return sk.lib().sketch_gen_matmul_noalloc(A, adt, m, n, lda, scales, seed, row0, col0, k, Y,
+                                              ydt, ldy, beta, stream)
+
+
+def test_noalloc_scratch_size_matches_header():
+    text = open(HEADERS[0]).read()
+    assert "#define SKETCH_NOALLOC_SCRATCH_BYTES (32u << 20)" in text
+
+
+@pytest.mark.parametrize("kw,expect", [
+    (dict(adt=3), EDTYPE), (dict(ydt=2), EDTYPE), (dict(m=-1), EINVAL), (dict(k=1025), EINVAL),
+    (dict(beta=2), EINVAL), (dict(Y=None), EINVAL), (dict(ldy=4), EINVAL), (dict(A=None), EINVAL),
+    (dict(lda=1000), EINVAL), (dict(row0=-1), EINVAL), (dict(A=PA + 4), EALIGN),
+    (dict(adt=FP8), EINVAL), (dict(m=70_000_000), EUNSUP),
+])
+def test_noalloc_rejects(kw, expect):
+    assert gm_noalloc(**kw) == expect
+
+
+def test_noalloc_rejects_calls_beyond_its_scratch():
+    # the largest m whose strip partials fit, and one row more (checked on the host)
+    per_row = sk.sketch_workspace_size(0, F32, 1, 32768, 5, 1)
+    m_max = NOALLOC_BYTES // per_row
+    assert sk.sketch_workspace_size(0, F32, m_max + 1, 32768, 5, 1) > NOALLOC_BYTES
+    assert gm_noalloc(m=m_max + 1, n=32768, lda=32768) == -11
+    assert gm_noalloc(m=1 << 20, n=1 << 15, lda=1 << 15, k=64, ldy=64) == -11
+    assert sk.sketch_status_string(-11) != "unknown status"
+    # m == 0 / k == 0 are no-ops that never touch the device
+    assert gm_noalloc(m=0, Y=None, A=None) == OK
+    assert gm_noalloc(k=0, Y=None, ldy=0) == OK
 
 
 def test_noop_shapes_return_ok_without_launch():
