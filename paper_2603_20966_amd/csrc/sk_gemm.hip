@@ -2,33 +2,34 @@
 //
 // The local product of Alg. 1 (GenRandom + local multiplication) and, for a
 // contraction split, the sum of the partial products (the Reduce-Scatter of
-// Alg. 1, done on the device), in one launch.
+// Alg. 1, done on the device).
 //
-// Work decomposition (one workgroup = one tile):
-//   * a strip of C consecutive columns of one A block (C = strip_width(kg))
-//     times a range of R rows, for a group of kg <= 16 Omega columns;
-//   * the workgroup first builds its C x kg slice of Omega in LDS (generated
-//     from the seed, or copied from an explicit Omega for the stored-operand
-//     variant), so Omega never exists in HBM on the generated path;
-//   * each wave then streams passes of 8 rows (32 rows apart between the
-//     four waves): all 64 lanes read one row segment per step, 16 contiguous
-//     bytes per lane (1 KB per load instruction), and multiply them by the
-//     matching Omega values from LDS with FP32 FMAs into per-lane
-//     accumulators (8 rows x kg columns per lane);
-//   * the first loads of A are issued before the Omega slice is generated,
-//     and each wave keeps two steps of nontemporal loads in flight across
-//     its passes;
+// Work decomposition (one workgroup of 8 waves = one tile):
+//   * a strip of C = 4096 consecutive columns of one A block times a range of
+//     R rows, for all k <= 8 Omega columns;
+//   * the strip is streamed in chunks of 1024 columns whose Omega slices live
+//     in a double-buffered LDS ring:
+//     generated from the seed (or copied from an explicit Omega for the
+//     stored-operand variant) one chunk ahead, so Omega never exists in HBM
+//     on the generated path and only the first chunk's generation is exposed;
+//   * each wave streams passes of 8 rows (64 rows apart between the eight
+//     waves): all 64 lanes read one row segment per step, 16 contiguous bytes
+//     per lane (1 KB per load instruction), and multiply them by the matching
+//     Omega values from LDS with FP32 FMAs into per-lane accumulators (8 rows
+//     x kg columns per lane); two steps of nontemporal loads stay in flight
+//     across passes and chunks;
 //   * at the end of a pass the 64 lanes' accumulators are summed by a fixed
 //     reduce-scatter (permlane32 and permlane16 swaps, then a DPP butterfly
-//     inside 16-lane rows), giving the FP32 partial of (row, strip, column);
-//     partials go to the workspace;
-//   * a second small kernel sums the partials of all strips in FP64, in strip
-//     order, adds beta * Y, rounds once and writes Y.  (No cross-workgroup
+//     inside 16-lane rows) and added, chunk after chunk, to the pass's FP32
+//     strip sums; after the last chunk they go to the workspace (or to Y);
+//   * a second small kernel sums the strip partials in FP64, in strip order,
+//     adds beta * Y, rounds once and writes Y.  (No cross-workgroup
 //     synchronisation inside the streaming kernel: device-scope release /
 //     acquire would write back and invalidate the L2 of an XCD under every
 //     streaming wave.)
-// The summation order depends only on the strip boundaries, never on m, R or
-// the grid, so results are bitwise reproducible and layout independent.
+// The summation order depends only on the strip and chunk boundaries, never
+// on m, R or the grid, so results are bitwise reproducible and layout
+// independent.
 #include "sk_device.hpp"
 #include "sk_internal.hpp"
 
@@ -116,6 +117,17 @@ __device__ __forceinline__ void unpack16(const uint4 raw, float* out) {
     }
 }
 
+// The same 16-byte nontemporal load through a buffer descriptor: `row` is a
+// wave-uniform address (scalar registers), voff the lane's byte offset, soff a
+// wave-uniform byte offset, so no vector instruction forms the address.
+__device__ __forceinline__ uint4 load_a16_row(const unsigned char* row, uint32_t voff,
+                                              uint32_t soff) {
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<unsigned char*>(row), (short)0, (int)0xFFFFFFFFu, 0x00020000);
+    const v4u32 v = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)voff, (int)soff, 2 /* nt */);
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+
 // Load up to 16 bytes at p of which only `nvalid` elements exist; the rest
 // read as zero.  Used for the ragged last step of a strip.
 template <int ADT>
@@ -176,119 +188,239 @@ struct Tile {
     bool single;              // the output has one strip: write Y directly
 };
 
-// One tile: issue the first A loads, build the Omega slice in LDS, stream the
-// rows, write the strip partials (or Y).  All threads of the workgroup call it.
+// LDS of one streaming workgroup: the double-buffered ring of Omega chunks and
+// every thread's running strip sums (one slot per pass and reduced value).
+template <int K>
+struct StreamLds {
+    static constexpr int CH = chunk_width(K);
+    static constexpr int Q = 2 * K;                   // reduced values per 16-lane row and pass
+    static constexpr int VPL = (Q + 15) / 16;         // reduced values per lane and pass
+    static constexpr int NP = stream_max_rows(K) / kRowQuantum;   // passes per wave
+    float om[2][K][CH];
+    float sacc[NP * VPL][kWgThreads];
+};
+
+// Sum each of the V = 8K accumulators of a pass over the 64 lanes as a
+// reduce-scatter.  permlane32_swap exchanges rows {2,3} of one register with
+// rows {0,1} of another, so one swap + add halves the values per lane (lanes
+// 0-31 keep the first half, lanes 32-63 the second); permlane16_swap does the
+// same between rows 0|1 and 2|3; a 4-stage DPP butterfly finishes each value
+// inside its 16-lane row.  Row r then holds values [r*V/4, (r+1)*V/4), lane
+// sig of the row value 16*b + sig of that range in mine[b]; every addition
+// order is fixed.
+template <int K>
+__device__ __forceinline__ void lane_reduce(const float (&acc)[kRowGroups][K], int lane,
+                                            float (&mine)[StreamLds<K>::VPL]) {
+    constexpr int V = kRowGroups * K;
+    constexpr int H = V / 2;
+    constexpr int Q = V / 4;
+    float hv[H];
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+        const int i0 = j / K, c0 = j % K, i1 = (j + H) / K, c1 = (j + H) % K;
+        const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(acc[i0][c0]),
+                                                         __float_as_uint(acc[i1][c1]), false, false);
+        hv[j] = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
+    }
+    float qv[Q];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+        const auto sw = __builtin_amdgcn_permlane16_swap(__float_as_uint(hv[j]),
+                                                         __float_as_uint(hv[j + Q]), false, false);
+        qv[j] = row16_sum(__uint_as_float(sw[0]) + __uint_as_float(sw[1]));
+    }
+    const int sig = lane & 15;
+#pragma unroll
+    for (int b = 0; b < StreamLds<K>::VPL; ++b) {
+        float m = 0.0f;
+#pragma unroll
+        for (int j = 16 * b; j < 16 * b + 16 && j < Q; ++j)
+            if (sig == j - 16 * b) m = qv[j];
+        mine[b] = m;
+    }
+}
+
+// One tile: a range of rows times one strip.  The strip is streamed chunk by
+// chunk; all threads generate the next chunk's Omega slice into the other half
+// of the LDS ring, a few quads at the start of each of their passes, while the
+// current chunk's loads are in flight; one LDS-only barrier per chunk.  Each
+// wave streams passes of 8 rows (64 rows apart between the eight waves): all 64
+// lanes read one row segment per step, 16 contiguous bytes per lane (1 KB per
+// load instruction), and multiply them by the matching Omega values from LDS
+// with FP32 FMAs into per-lane accumulators; loads run two steps ahead across
+// pass and chunk boundaries.  At the end of a pass the 64 lanes' accumulators
+// are reduced (lane_reduce) and added, in chunk order, to the pass's running
+// FP32 strip sums in LDS; after the last chunk the strip sums go to the
+// workspace (or to Y when the call has one strip).  All threads call it.
 template <int K, int ADT, bool GEN>
-__device__ __forceinline__ void tile_body(const Tile& tl, float (*om)[strip_width(K, ADT)]) {
+__device__ __forceinline__ void tile_body(const Tile& tl, StreamLds<K>& L) {
     constexpr int es = Elem<ADT>::size;
     constexpr int EPL = 16 / es;                 // elements per lane step
     constexpr int C = strip_width(K, ADT);       // columns per strip
+    constexpr int CH = StreamLds<K>::CH;         // columns per chunk
     constexpr int STEP = kLanesPerRow * EPL;     // columns per wave step
-    constexpr int T = C / STEP;                  // steps per full strip
-    static_assert(C % STEP == 0, "strip must hold whole steps");
+    constexpr int TS = CH / STEP;                // steps per chunk
+    constexpr int KD = TS >= kDepth ? kDepth : 1;
+    constexpr int VPL = StreamLds<K>::VPL;
+    constexpr int Q = StreamLds<K>::Q;
+    static_assert(C % CH == 0 && CH % STEP == 0 && TS % KD == 0, "strip = whole chunks = whole steps");
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = tid >> 6;
+    // wave-uniform, so that row indices and row addresses live in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int kg = tl.kg;
     const int c_base = tl.c_base;
     const int64_t col_begin = tl.col_begin;
-    const int w = (int)min<int64_t>(C, tl.n - col_begin);
+    const int w = (int)min<int64_t>(C, tl.n - col_begin);   // columns of this strip
+    const int nch = (w + CH - 1) / CH;
     const int64_t row_end = tl.row_end;
-
-    // ---- this wave's rows: passes of 8 rows, 32 rows apart ------------------
     const int64_t lda_bytes = tl.lda * es;
-    const bool full = (w == C);
-    const int Tr = full ? T : (w + STEP - 1) / STEP;    // steps per pass
     const int64_t first_pb = tl.row_begin + wave * kRowGroups;
     const int npass = first_pb < row_end ? (int)((row_end - first_pb + kRowQuantum - 1) / kRowQuantum) : 0;
-    const unsigned char* lane_col = tl.A + (col_begin + lane * EPL) * es;
+    const unsigned char* strip_base = tl.A + col_begin * es;
+    const int m_last = __builtin_amdgcn_readfirstlane((int)(tl.m - 1));
+    const uint32_t lane_off = (uint32_t)lane * 16u;       // bytes
 
-    // Steps run pass by pass (8 rows), column step by column step; loads are
-    // issued kDepth steps ahead of the FMAs that consume them.
-    int ip = 0, it_ = 0;   // next step to load: pass, column step
-    int cp = 0, ct = 0;    // next step to consume
+    // ---- A loads: step (chunk j, pass p, step t) reads 8 rows of this wave at
+    //      strip columns j*CH + t*STEP + [lane*EPL, lane*EPL + EPL); the row
+    //      address is wave-uniform, the lane offset a 32-bit vector offset ------
+    int ij = npass > 0 ? 0 : nch, ip = 0, it_ = 0;   // next step to load
     auto issue = [&](uint4* buf) {
-        if (ip >= npass) return;
-        const int p = ip;
-        const int t = it_;
-        if (++it_ == Tr) {
-            it_ = 0;
-            ++ip;
-        }
-        const int64_t pb = first_pb + (int64_t)p * kRowQuantum;
-        const int cl = t * STEP + lane * EPL;
+        if (ij >= nch) return;
+        const int64_t pb = first_pb + (int64_t)ip * kRowQuantum;
+        const int off = ij * CH + it_ * STEP;
+        const unsigned char* colp = strip_base + (int64_t)off * es;
+        if (off + STEP <= w) {
+            // rows are below 2^31 (the host checks bound m); every quantity here is wave-uniform
+            const int pr = __builtin_amdgcn_readfirstlane((int)pb);
 #pragma unroll
-        for (int i = 0; i < kRowGroups; ++i) {
-            const int64_t r = min<int64_t>(pb + i, tl.m - 1);
-            const unsigned char* ptr = lane_col + r * lda_bytes + (int64_t)t * STEP * es;
-            if (full || w - cl >= EPL) buf[i] = load_a16(ptr);
-            else buf[i] = load_tail<ADT>(ptr, w - cl);
+            for (int i = 0; i < kRowGroups; ++i) {
+                const int r = min(pr + i, m_last);
+                buf[i] = load_a16_row(strip_base + (int64_t)r * lda_bytes, lane_off,
+                                      (uint32_t)(off * es));
+            }
+        } else {
+            // ragged end of the strip: only the valid elements are read
+            const int left = w - off - lane * EPL;      // valid elements from this lane's first
+#pragma unroll
+            for (int i = 0; i < kRowGroups; ++i) {
+                const unsigned char* ptr = colp + min<int64_t>(pb + i, tl.m - 1) * lda_bytes + lane_off;
+                buf[i] = left >= EPL ? load_a16(ptr)
+                         : left > 0  ? load_tail<ADT>(ptr, left)
+                                     : make_uint4(0u, 0u, 0u, 0u);
+            }
+        }
+        if (++it_ == TS) {
+            it_ = 0;
+            if (++ip == npass) {
+                ip = 0;
+                ++ij;
+            }
         }
     };
 
-    uint4 bufs[kDepth][kRowGroups];
+    // ---- Omega chunk j -> L.om[j & 1]: items [i0, i1) of this thread's list ----
+    // Generated: item = (Philox quad qi, column c), four consecutive Omega rows;
+    // stored operand: item = (column jl of the chunk, Omega column c).
+    const int64_t g0 = tl.row0 + col_begin;                  // global Omega row of strip column 0
+    auto chunk_items = [&](int j) {
+        const int wj = min(CH, w - j * CH);
+        if constexpr (GEN) {
+            const int64_t gj = g0 + (int64_t)j * CH;
+            return (int)(((gj + wj - 1) >> 2) - (gj >> 2) + 1) * kg;
+        } else {
+            return wj * kg;
+        }
+    };
+    auto gen_items = [&](int j, int i0, int i1) {
+        float (*om)[CH] = L.om[j & 1];
+        const int wj = min(CH, w - j * CH);
+        const int items = chunk_items(j);
+        const int64_t gj = g0 + (int64_t)j * CH;
+        for (int i = i0; i < i1; ++i) {
+            const int it = tid + i * kWgThreads;
+            if (it >= items) break;
+            if constexpr (GEN) {
+                const int64_t q_lo = gj >> 2;
+                const int qi = it / kg;
+                const int c = it - qi * kg;
+                const float4 z = omega4_dist((uint64_t)(q_lo + qi), tl.col0 + (uint32_t)(c_base + c),
+                                             tl.key0, tl.key1, tl.dist);
+                const int64_t p0 = 4 * (q_lo + qi) - gj;          // chunk column of z.x
+                if ((gj & 3) == 0 && p0 + 3 < wj) {
+                    *reinterpret_cast<float4*>(&om[c][p0]) = z;
+                } else {
+                    const float zz[4] = {z.x, z.y, z.z, z.w};
 #pragma unroll
-    for (int d = 0; d < kDepth; ++d) issue(bufs[d]);
-
-    // ---- Omega slice for this strip -> LDS (overlaps the first loads) --------
-    if constexpr (GEN) {
-        const int64_t g0 = tl.row0 + col_begin;            // global Omega row of column 0
-        const int64_t q_lo = g0 >> 2;
-        const int64_t q_hi = (g0 + w - 1) >> 2;
-        const int nq = (int)(q_hi - q_lo + 1);
-        const int items = nq * kg;
-        const bool aligned = (g0 & 3) == 0;
-        for (int it = tid; it < items; it += kWgThreads) {
-            const int qi = it / kg;
-            const int c = it - qi * kg;
-            const float4 z = omega4_dist((uint64_t)(q_lo + qi), tl.col0 + (uint32_t)(c_base + c),
-                                         tl.key0, tl.key1, tl.dist);
-            const int64_t p0 = 4 * (q_lo + qi) - g0;       // local column of z.x
-            if (aligned && p0 + 3 < w) {
-                *reinterpret_cast<float4*>(&om[c][p0]) = z;
-            } else {
-                const float zz[4] = {z.x, z.y, z.z, z.w};
-#pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    const int64_t p = p0 + t;
-                    if (p >= 0 && p < w) om[c][p] = zz[t];
+                    for (int t = 0; t < 4; ++t) {
+                        const int64_t p = p0 + t;
+                        if (p >= 0 && p < wj) om[c][p] = zz[t];
+                    }
                 }
+            } else {
+                const int jl = it / kg;
+                const int c = it - jl * kg;
+                om[c][jl] = tl.omega[(col_begin + (int64_t)j * CH + jl) * tl.ldo + c_base + c];
             }
         }
-    } else {
-        for (int it = tid; it < w * kg; it += kWgThreads) {
-            const int jl = it / kg;
-            const int c = it - jl * kg;
-            om[c][jl] = tl.omega[(col_begin + jl) * tl.ldo + c_base + c];
+    };
+    // zero what a ragged chunk or a partial column group leaves unwritten
+    auto zero_unused = [&](int j) {
+        const int wj = min(CH, w - j * CH);
+        if (wj == CH && kg == K) return;
+        float (*om)[CH] = L.om[j & 1];
+        for (int it = tid; it < K * CH; it += kWgThreads) {
+            const int c = it / CH;
+            const int jl = it - c * CH;
+            if (c >= kg || jl >= wj) om[c][jl] = 0.0f;
         }
-    }
-    // zero the unused part of the slice (ragged strip, unused columns)
-    for (int it = tid; it < K * C; it += kWgThreads) {
-        const int c = it / C;
-        const int jl = it - c * C;
-        if (c >= kg || jl >= w) om[c][jl] = 0.0f;
-    }
+    };
+
+    uint4 bufs[KD][kRowGroups];
+#pragma unroll
+    for (int d = 0; d < KD; ++d) issue(bufs[d]);
+
+    // chunk 0 while the first loads are in flight
+    gen_items(0, 0, (chunk_items(0) + kWgThreads - 1) / kWgThreads);
+    zero_unused(0);
     lds_barrier();
 
-    // ---- stream: FMA each step, 64-lane sums at the end of each pass ---------
+    // This thread's share of chunk j + 1 (cnt items), spread over the wave's
+    // steps of chunk j: ips items after each step's load is issued.
+    int cnt = 0, ips = 0, gi = 0;
+    auto plan_next = [&](int j) {
+        cnt = j + 1 < nch ? (chunk_items(j + 1) + kWgThreads - 1) / kWgThreads : 0;
+        const int steps = npass * TS;
+        ips = steps > 0 ? (cnt + steps - 1) / steps : cnt;
+        gi = 0;
+    };
+
+    if (npass == 0) {
+        // no rows for this wave: it only helps to build the chunks
+        for (int j = 0; j + 1 < nch; ++j) {
+            plan_next(j);
+            gen_items(j + 1, 0, cnt);
+            zero_unused(j + 1);
+            lds_barrier();
+        }
+    } else {
+        plan_next(0);
+    }
+
     float acc[kRowGroups][K];
 #pragma unroll
     for (int i = 0; i < kRowGroups; ++i)
 #pragma unroll
         for (int c = 0; c < K; ++c) acc[i][c] = 0.0f;
 
-    auto consume = [&](const uint4* raw) {
-        const int p = cp;
-        const int t = ct;
-        if (++ct == Tr) {
-            ct = 0;
-            ++cp;
-        }
+    int cj = 0, cp = 0, ct = 0;   // next step to consume: chunk, pass, step
+    auto fma_step = [&](const uint4* raw) {
+        const float (*om)[CH] = L.om[cj & 1];
         float a[kRowGroups][EPL];
 #pragma unroll
         for (int i = 0; i < kRowGroups; ++i) unpack16<ADT>(raw[i], a[i]);
-        const int cl = t * STEP + lane * EPL;
+        const int cl = ct * STEP + lane * EPL;
 #pragma unroll
         for (int c = 0; c < K; ++c) {
             float wv[EPL];
@@ -305,76 +437,80 @@ __device__ __forceinline__ void tile_body(const Tile& tl, float (*om)[strip_widt
 #pragma unroll
                 for (int e = 0; e < EPL; ++e) acc[i][c] = __builtin_fmaf(a[i][e], wv[e], acc[i][c]);
         }
-        if (t != Tr - 1) return;
-        // End of pass: sum each of the V = 8K accumulators over the 64 lanes as a
-        // reduce-scatter.  permlane32_swap exchanges rows {2,3} of one register
-        // with rows {0,1} of another, so one swap + add halves the values per
-        // lane (lanes 0-31 keep the first half, lanes 32-63 the second);
-        // permlane16_swap does the same between rows 0|1 and 2|3; a 4-stage DPP
-        // butterfly finishes each value inside its 16-lane row.  Row r then
-        // holds values [r*V/4, (r+1)*V/4); every addition order is fixed.
-        const int64_t pb = first_pb + (int64_t)p * kRowQuantum;
-        constexpr int V = kRowGroups * K;
-        constexpr int H = V / 2;
-        constexpr int Q = V / 4;
-        float hv[H];
-#pragma unroll
-        for (int j = 0; j < H; ++j) {
-            const int i0 = j / K, c0 = j % K, i1 = (j + H) / K, c1 = (j + H) % K;
-            const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(acc[i0][c0]),
-                                                             __float_as_uint(acc[i1][c1]), false, false);
-            hv[j] = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
+    };
+    // after a step: a slice of the next chunk, then the pass / chunk bookkeeping
+    auto advance = [&]() {
+        if (gi < cnt) {
+            gen_items(cj + 1, gi, min(cnt, gi + ips));
+            gi += ips;
         }
-        float qv[Q];
+        if (++ct < TS) return;
+        // end of a pass: 64-lane sums, added to the pass's strip sums in chunk order
+        ct = 0;
+        float mine[VPL];
+        lane_reduce<K>(acc, lane, mine);
 #pragma unroll
-        for (int j = 0; j < Q; ++j) {
-            const auto sw = __builtin_amdgcn_permlane16_swap(__float_as_uint(hv[j]),
-                                                             __float_as_uint(hv[j + Q]), false, false);
-            qv[j] = row16_sum(__uint_as_float(sw[0]) + __uint_as_float(sw[1]));
-        }
-        const int row16 = lane >> 4;
-        const int vbase = (row16 >> 1) * H + (row16 & 1) * Q;
-        const int sig = lane & 15;
-#pragma unroll
-        for (int base = 0; base < Q; base += 16) {
-            float mine = 0.0f;
-#pragma unroll
-            for (int j = base; j < base + 16 && j < Q; ++j)
-                if (sig == j - base) mine = qv[j];
-            const int v = vbase + base + sig;        // accumulator index i*K + c
-            const int wi = v / K;
-            const int wc = v - wi * K;
-            const int64_t r = pb + wi;
-            if (base + sig < Q && r < row_end && wc < kg) {
-                if (tl.scales) mine *= tl.scales[r >> 7];
-                if (tl.single) {
-                    double y = (double)mine;
-                    if (tl.y_f64) {
-                        double* Yp = static_cast<double*>(tl.Y) + r * tl.ldy + c_base + wc;
-                        if (tl.beta) y += *Yp;
-                        *Yp = y;
-                    } else {
-                        float* Yp = static_cast<float*>(tl.Y) + r * tl.ldy + c_base + wc;
-                        if (tl.beta) y += (double)*Yp;
-                        *Yp = (float)y;
-                    }
-                } else {
-                    tl.partials[(tl.strip_index * tl.m + r) * tl.k + c_base + wc] = mine;
-                }
-            }
+        for (int b = 0; b < VPL; ++b) {
+            float& sv = L.sacc[cp * VPL + b][tid];
+            sv = (cj == 0) ? mine[b] : sv + mine[b];
         }
 #pragma unroll
         for (int i = 0; i < kRowGroups; ++i)
 #pragma unroll
             for (int c = 0; c < K; ++c) acc[i][c] = 0.0f;
+        if (++cp < npass) return;
+        // end of a chunk: the next one is complete once every wave is here
+        cp = 0;
+        if (cj + 1 < nch) {
+            if (gi < cnt) gen_items(cj + 1, gi, cnt);
+            zero_unused(cj + 1);
+            lds_barrier();
+        }
+        ++cj;
+        plan_next(cj);
     };
 
-    while (cp < npass) {
+    if (npass > 0) {
+        while (cj < nch) {
 #pragma unroll
-        for (int d = 0; d < kDepth; ++d) {
-            if (cp < npass) {
-                consume(bufs[d]);
-                issue(bufs[d]);
+            for (int d = 0; d < KD; ++d) {
+                if (cj < nch) {
+                    fma_step(bufs[d]);
+                    issue(bufs[d]);
+                    advance();
+                }
+            }
+        }
+    }
+
+    // ---- strip sums -> workspace (or Y) ----------------------------------------
+    const int row16 = lane >> 4;
+    const int sig = lane & 15;
+    const int vbase = (row16 >> 1) * (kRowGroups * K / 2) + (row16 & 1) * Q;
+    for (int p = 0; p < npass; ++p) {
+        const int64_t pb = first_pb + (int64_t)p * kRowQuantum;
+#pragma unroll
+        for (int b = 0; b < VPL; ++b) {
+            const int v = vbase + 16 * b + sig;        // accumulator index i*K + c
+            const int wi = v / K;
+            const int wc = v - wi * K;
+            const int64_t r = pb + wi;
+            if (16 * b + sig >= Q || r >= row_end || wc >= kg) continue;
+            float val = L.sacc[p * VPL + b][tid];
+            if (tl.scales) val *= tl.scales[r >> 7];
+            if (tl.single) {
+                double y = (double)val;
+                if (tl.y_f64) {
+                    double* Yp = static_cast<double*>(tl.Y) + r * tl.ldy + c_base + wc;
+                    if (tl.beta) y += *Yp;
+                    *Yp = y;
+                } else {
+                    float* Yp = static_cast<float*>(tl.Y) + r * tl.ldy + c_base + wc;
+                    if (tl.beta) y += (double)*Yp;
+                    *Yp = (float)y;
+                }
+            } else {
+                tl.partials[(tl.strip_index * tl.m + r) * tl.k + c_base + wc] = val;
             }
         }
     }
@@ -393,7 +529,7 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t id, int64_t T8) {
 template <int K, int ADT, bool GEN>
 __global__ __launch_bounds__(kWgThreads) void k_gemm_stream(const KArgs args) {
     constexpr int C = strip_width(K, ADT);
-    __shared__ float om[K][C];
+    __shared__ StreamLds<K> lds;
     const int64_t t = xcd_tile(blockIdx.x, args.tiles8);
     if (t >= args.tiles) return;
     const int strip = (int)(t % args.S_total);
@@ -434,7 +570,7 @@ __global__ __launch_bounds__(kWgThreads) void k_gemm_stream(const KArgs args) {
     tl.partials = args.partials;
     tl.strip_index = strip;
     tl.single = (args.S_total == 1);
-    tile_body<K, ADT, GEN>(tl, om);
+    tile_body<K, ADT, GEN>(tl, lds);
 }
 
 // A batch of independent requests (serving): the same tiles as one call per
@@ -443,7 +579,7 @@ __global__ __launch_bounds__(kWgThreads) void k_gemm_stream(const KArgs args) {
 template <int K, int ADT>
 __global__ __launch_bounds__(kWgThreads) void k_gemm_batch(const BatchArgs args) {
     constexpr int C = strip_width(K, ADT);
-    __shared__ float om[K][C];
+    __shared__ StreamLds<K> lds;
     bool first = true;
     const int64_t T8 = (args.total_tiles + 7) / 8;
     for (int64_t v = blockIdx.x; v < 8 * T8; v += gridDim.x) {   // gridDim.x is a multiple of 8
@@ -482,9 +618,9 @@ __global__ __launch_bounds__(kWgThreads) void k_gemm_batch(const BatchArgs args)
         tl.partials = rq.partials;
         tl.strip_index = strip;
         tl.single = (rq.strips == 1);
-        if (!first) lds_barrier();   // every wave is done with the previous slice
+        if (!first) lds_barrier();   // every wave is done with the previous tile's LDS
         first = false;
-        tile_body<K, ADT, true>(tl, om);
+        tile_body<K, ADT, true>(tl, lds);
     }
 }
 
@@ -576,9 +712,7 @@ hipError_t dispatch_k(int kc, const KArgs& a, dim3 grid, hipStream_t s, const Tr
     case 4: return launch_k<4, ADT, GEN>(a, grid, s, tr);
     case 5: return launch_k<5, ADT, GEN>(a, grid, s, tr);
     case 6: return launch_k<6, ADT, GEN>(a, grid, s, tr);
-    case 8: return launch_k<8, ADT, GEN>(a, grid, s, tr);
-    case 12: return launch_k<12, ADT, GEN>(a, grid, s, tr);
-    default: return launch_k<16, ADT, GEN>(a, grid, s, tr);
+    default: return launch_k<8, ADT, GEN>(a, grid, s, tr);
     }
 }
 
@@ -600,20 +734,27 @@ int device_cus() {
     return cus[dev];
 }
 
-// Rows per tile: a multiple of 32 giving about two tiles per compute unit,
-// at most 512 rows (measured best on the 4096 x 32768 share and on the
-// 32768 x 32768 column layout).  SKETCH_ROWS_PER_TILE overrides it for tuning.
-int64_t rows_per_tile(int64_t m, int64_t strips, int64_t ncg) {
+// Rows per tile: a multiple of the pass height giving about one tile (one
+// workgroup of 8 waves, the most that the kernel's registers let a compute
+// unit hold) per compute unit, or two when that would leave tiles of fewer
+// than 256 rows (a 4096 x 32768 share: 64-row tiles in two rounds measured
+// 93 us against 129 us for one round of 128-row tiles, whose per-unit
+// bandwidth spread then sets the end), at most max_rows (the per-pass strip
+// sums of a tile live in LDS).  SKETCH_ROWS_PER_TILE overrides it for tuning
+// (still capped at max_rows).
+int64_t rows_per_tile(int64_t m, int64_t strips, int64_t ncg, int64_t max_rows) {
     static const int64_t forced = [] {
         const char* e = getenv("SKETCH_ROWS_PER_TILE");
         const long long v = e ? atoll(e) : 0;
         return (int64_t)(v > 0 ? v : 0);
     }();
-    const int64_t want = 2 * (int64_t)device_cus();
-    int64_t R = forced > 0 ? forced : (m * strips * ncg + want - 1) / want;
+    const int64_t cus = (int64_t)device_cus();
+    const int64_t work = m * strips * ncg;
+    int64_t R = (work + cus - 1) / cus;
+    if (R < 256) R = (work + 2 * cus - 1) / (2 * cus);
+    if (forced > 0) R = forced;
     R = (R + kRowQuantum - 1) / kRowQuantum * kRowQuantum;
-    if (forced == 0) R = std::min<int64_t>(R, 512);
-    return std::max<int64_t>(kRowQuantum, R);
+    return std::max<int64_t>(kRowQuantum, std::min<int64_t>(R, max_rows));
 }
 
 int64_t count_strips(const GemmLaunch& g) {
@@ -641,9 +782,9 @@ hipError_t launch_reduce_partials(const float* partials, int S, int64_t m, int64
 }
 
 hipError_t launch_gemm_stream(const GemmLaunch& g) {
-    const int64_t ncg = (g.k + kColGroup - 1) / kColGroup;
-    const int kg0 = (int)std::min<int64_t>(g.k, kColGroup);
-    const int kc = k_class(kg0);
+    if (g.k > kStreamMaxK) return hipErrorInvalidValue;   // wider sketches run on the matrix cores
+    const int64_t ncg = 1;
+    const int kc = k_class((int)g.k);
     const int64_t S = count_strips(g);
     KArgs a{};
     a.m = g.m;
@@ -662,7 +803,7 @@ hipError_t launch_gemm_stream(const GemmLaunch& g) {
     a.beta = g.beta;
     for (int b = 0; b < g.P; ++b) a.blk[b] = g.blk[b];
     const bool gen = (g.omega == nullptr);
-    const int64_t R = rows_per_tile(g.m, S, ncg);
+    const int64_t R = rows_per_tile(g.m, S, ncg, stream_max_rows(kc));
     const int64_t nrb = (g.m + R - 1) / R;
     a.rows_per_wg = (int)R;
     a.num_rb = (int)nrb;
@@ -671,10 +812,11 @@ hipError_t launch_gemm_stream(const GemmLaunch& g) {
     if (S > 1) a.partials = static_cast<float*>(g.workspace);
     dim3 grid((unsigned)(8 * a.tiles8));
     const TraceEvents& tr = g.trace;
+    // FP8 A always runs on the low-precision matrix-core kernel
     switch (g.adtype) {
     case 0: return gen ? dispatch_k<0, true>(kc, a, grid, g.stream, tr) : dispatch_k<0, false>(kc, a, grid, g.stream, tr);
     case 1: return gen ? dispatch_k<1, true>(kc, a, grid, g.stream, tr) : dispatch_k<1, false>(kc, a, grid, g.stream, tr);
-    default: return gen ? dispatch_k<2, true>(kc, a, grid, g.stream, tr) : dispatch_k<2, false>(kc, a, grid, g.stream, tr);
+    default: return hipErrorInvalidValue;
     }
 }
 
@@ -721,8 +863,6 @@ hipError_t run_batch_k(int kclass, const BatchArgs& a, int grid, hipStream_t s) 
     case 5: return run_batch<5, ADT>(a, grid, s);
     case 6: return run_batch<6, ADT>(a, grid, s);
     case 8: return run_batch<8, ADT>(a, grid, s);
-    case 12: return run_batch<12, ADT>(a, grid, s);
-    case 16: return run_batch<16, ADT>(a, grid, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -738,7 +878,7 @@ hipError_t launch_gemm_batch(const BatchArgs& a, int kclass, int adtype, int gri
     if (a.count == 0 || a.total_tiles == 0) return hipSuccess;
     hipError_t e = adtype == 0   ? run_batch_k<0>(kclass, a, grid, s)
                    : adtype == 1 ? run_batch_k<1>(kclass, a, grid, s)
-                                 : run_batch_k<2>(kclass, a, grid, s);
+                                 : hipErrorInvalidValue;   // FP8: matrix-core batches only
     if (e != hipSuccess) return e;
     return launch_reduce_batch(a, s);
 }

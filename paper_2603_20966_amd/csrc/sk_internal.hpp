@@ -10,54 +10,63 @@ namespace sk {
 
 constexpr int kMaxBlocks = 64;     // contraction blocks per reduce call
 constexpr int kColGroup = 16;      // Omega columns handled by one workgroup
-constexpr int kWgThreads = 256;    // threads per workgroup of the streaming kernel
-constexpr int kRowQuantum = 32;    // rows per workgroup pass (4 waves x 8 rows)
+constexpr int kStreamWaves = 8;                  // waves per workgroup of the streaming kernel
+constexpr int kWgThreads = 64 * kStreamWaves;    // its threads
+constexpr int kRowQuantum = 8 * kStreamWaves;    // rows per workgroup pass (8 rows per wave)
 
 // Register-tile class (template K of the streaming kernel) for a group of
 // kg Omega columns.
 constexpr int k_class(int kg) { return kg <= 6 ? kg : kg <= 8 ? 8 : kg <= 12 ? 12 : 16; }
 
-// Strip width (columns of A per workgroup, and per FP32 partial sum) of the
-// streaming kernel.  A function of the tile class and the storage type only,
-// so results never depend on m or on the launch shape.  It holds whole wave
-// steps (64 lanes x 16 bytes) and keeps the Omega slice (kclass x width
-// floats) within 64 KiB of LDS; narrower types get wider strips so the
-// 64-lane sums stay amortised over as many elements.  Wide strips also keep
-// the partial sums few (k / width of the A bytes), whose HBM writes slow the
-// read stream far beyond their share: FP32 at k = 9 .. 16 runs 10% faster
-// with 1024 columns than with 512 (measured on 32768^2).
-constexpr int strip_width(int kclass, int adtype) {
-    return adtype == 0 ? 1024
-         : adtype == 1 ? (kclass <= 8 ? 2048 : 1024)
-                       : (kclass <= 4 ? 4096 : kclass <= 8 ? 2048 : 1024);
-}
+// Strip width (columns of A per FP32 partial sum) of the streaming kernel:
+// 4096 columns for FP32 and BF16 A at every k <= 16.  A function of the
+// storage type only, so results never depend on m or on the launch shape.
+// The partial sums' HBM writes slow the read stream far beyond their share of
+// the bytes (scattered writes in the middle of a read stream): 1024-column
+// strips cost about 10% of the A stream at k = 5, so the strips are as wide
+// as the 4096-column blocks of a contraction split of 32768 columns over 8
+// processes, whose bitwise agreement with the row layout needs the block
+// width to be a multiple of the strip width.
+constexpr int strip_width(int /*kclass*/, int /*adtype*/) { return 4096; }
 
-// The matrix-core kernel takes FP32 A once k exceeds one column group (16).
-// At k = 16 the VALU path is still faster (measured on 65536 x 16384:
-// 4.1 TB/s on VALU, 2.9 TB/s with one 16-column matrix-core tile).  Its strips
-// are 2048 columns.
+// A strip is streamed as chunks of 1024 columns: each chunk's Omega slice
+// (kclass x chunk floats) sits in one half of a double-buffered LDS ring, the
+// next chunk's slice being generated while the current one is multiplied.
+// The 64-lane sums close each chunk; a strip's FP32 partial is the sum of its
+// chunk sums in chunk order.  A function of the tile class only.
+constexpr int chunk_width(int /*kclass*/) { return 1024; }
+
+// Most rows one streaming tile covers (the per-pass strip sums of a wave live
+// in LDS: 16 passes of 8 rows per wave).
+constexpr int stream_max_rows(int /*kclass*/) { return 16 * 8 * kStreamWaves; }
+
+// The matrix-core kernel takes FP32 A from k = 9 on: past 8 sketch columns
+// the non-packed FP32 FMAs of the streaming kernel (4k per 16 bytes of A)
+// approach the vector ALU's rate at HBM speed, and its registers no longer
+// hold 8 rows of k accumulators.  Its strips are 2048 columns.
 constexpr int kMfmaStrip = 2048;
 constexpr int kMfmaRows = 512;     // rows of a matrix-core tile
-constexpr int kMfmaMinK = kColGroup + 1;
+constexpr int kStreamMaxK = 8;     // widest sketch of the streaming kernel
+constexpr int kMfmaMinK = kStreamMaxK + 1;
 constexpr bool use_mfma(int adtype, int64_t k) { return adtype == 0 && k >= kMfmaMinK; }
 
 // Low-precision A on the BF16 matrix cores: FP8 at every k (on the VALU path
 // its conversions and 5 FMAs per byte cap k = 5 at 2.6 TB/s, against 3.2 TB/s
-// here), BF16 past one column group (at k = 5 both paths measured the same
-// speed, and the VALU path sums with FP32 Omega: 1e-7 against 2.5e-6 relative
-// arithmetic error).  Strips of 4096 columns.
+// here), BF16 from k = 9 on (at k = 5 both paths measured the same speed, and
+// the VALU path sums with FP32 Omega: 1e-7 against 2.5e-6 relative arithmetic
+// error).  Strips of 4096 columns.
 constexpr int kLpStrip = 4096;
 constexpr int kLpBatchWaves = 8;                  // waves per tile in batched launches
 constexpr int kLpBatchRows = 64 * kLpBatchWaves;  // rows per tile in batched launches
 constexpr bool use_mfma_lp(int adtype, int64_t k) {
-    return adtype == 2 || (adtype == 1 && k > kColGroup);
+    return adtype == 2 || (adtype == 1 && k > kStreamMaxK);
 }
 
 // Strip width used for a sketch of width k with A stored as adtype.
 constexpr int64_t strip_width_for(int adtype, int64_t k) {
     return use_mfma(adtype, k)      ? kMfmaStrip
            : use_mfma_lp(adtype, k) ? kLpStrip
-                                    : strip_width(k_class((int)(k < kColGroup ? k : kColGroup)), adtype);
+                                    : strip_width(k_class((int)(k < kStreamMaxK ? k : kStreamMaxK)), adtype);
 }
 
 struct BlockDesc {
@@ -169,7 +178,7 @@ int batch_grid(int per_cu, int64_t total_tiles, int grid);
 // Compute units of the current device; rows per streaming tile for m rows,
 // `strips` strips and ncg column groups.
 int device_cus();
-int64_t rows_per_tile(int64_t m, int64_t strips, int64_t ncg);
+int64_t rows_per_tile(int64_t m, int64_t strips, int64_t ncg, int64_t max_rows);
 // A[i][j] ~ N(0,1) for a synthetic request: Philox4x32-10 on counters
 // (j/4, i, 0, 1) (the last word keeps the stream apart from Omega's, whose
 // last word is 0), Box-Muller with the hardware transcendentals.

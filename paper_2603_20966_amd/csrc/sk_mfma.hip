@@ -976,6 +976,7 @@ hipError_t launch_m(const MArgs& a, dim3 grid, hipStream_t s) {
 template <bool GEN>
 hipError_t dispatch_m(int nt, const MArgs& a, dim3 grid, hipStream_t s) {
     switch (nt) {
+    case 1: return launch_m<1, GEN>(a, grid, s);
     case 2: return launch_m<2, GEN>(a, grid, s);
     case 4: return launch_m<4, GEN>(a, grid, s);
     default: return launch_m<8, GEN>(a, grid, s);
@@ -985,7 +986,7 @@ hipError_t dispatch_m(int nt, const MArgs& a, dim3 grid, hipStream_t s) {
 }  // namespace
 
 // N-tiles (of 16 sketch columns) per workgroup for a sketch of width k.
-int mfma_ntiles(int64_t k) { return k <= 32 ? 2 : k <= 64 ? 4 : 8; }
+int mfma_ntiles(int64_t k) { return k <= 16 ? 1 : k <= 32 ? 2 : k <= 64 ? 4 : 8; }
 
 hipError_t launch_gemm_mfma(const GemmLaunch& g) {
     const int nt = mfma_ntiles(g.k);
@@ -1045,6 +1046,7 @@ hipError_t launch_gemm_mfma_batch(const BatchArgs& a, int nt, int grid, hipStrea
     if (a.count == 0 || a.total_tiles == 0) return hipSuccess;
     hipError_t e;
     switch (nt) {
+    case 1: e = run_mfma_batch<1>(a, grid, s); break;
     case 2: e = run_mfma_batch<2>(a, grid, s); break;
     case 4: e = run_mfma_batch<4>(a, grid, s); break;
     case 8: e = run_mfma_batch<8>(a, grid, s); break;

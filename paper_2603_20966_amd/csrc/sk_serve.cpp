@@ -213,7 +213,8 @@ void launch_batch(sk_server* S, const sk::Batch& b, const std::vector<ServerReq*
         x.strips = (int32_t)q.g.strips;
         x.rows_per_wg = (int32_t)(q.g.path != Geometry::kStream
                                       ? q.g.rows
-                                      : sk::rows_per_tile(r.m, q.g.strips, q.g.ncols));
+                                      : sk::rows_per_tile(r.m, q.g.strips, q.g.ncols,
+                                                          sk::stream_max_rows(q.g.kclass)));
         x.rowblocks = (int32_t)((r.m + x.rows_per_wg - 1) / x.rows_per_wg);
         x.tile_begin = tiles;
         x.out_begin = outs;

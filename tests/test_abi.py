@@ -76,7 +76,7 @@ def gm(A=PA, adt=F32, m=64, n=1024, lda=1024, scales=None, seed=1, row0=0, col0=
     (dict(m=40_000_000, k=64, ldy=64), EUNSUP),           # matrix-core grid limit (65535 x 512 rows)
 ])
 def test_gen_matmul_rejects(kw, expect):
-    args = dict(n=4096, lda=4096)
+    args = dict(n=8192, lda=8192)      # two 4096-column strips: a workspace is needed
     args.update(kw)
     assert gm(**args) == expect
 
@@ -220,23 +220,24 @@ def test_column_major_and_second_product_reject_on_host():
 
 def test_workspace_size_rules():
     ws = sk.sketch_workspace_size
-    assert ws(0, F32, 4096, 1024, 5, 1) == 0          # one strip: written directly, no partials
+    assert ws(0, F32, 4096, 4096, 5, 1) == 0          # one strip: written directly, no partials
     a = ws(0, F32, 4096, 32768, 5, 1)
-    assert a == 32 * 4096 * 5 * 4                       # 32 strips of 1024 columns
+    assert a == 8 * 4096 * 5 * 4                        # 8 strips of 4096 columns
     b = ws(1, F32, 32768, 32768, 5, 8)
-    assert b >= (32 + 8) * 32768 * 5 * 4                # bound valid for any 8-way split
+    assert b >= (8 + 8) * 32768 * 5 * 4                 # bound valid for any 8-way split
     assert ws(2, F32, 1, 1, 1, 1) == 0 and ws(0, 5, 1, 1, 1, 1) == 0 and ws(1, F32, 1, 1, 1, 0) == 0
     assert ws(0, F32, 100, 5000, 1025, 1) == 0          # k > 1024 is invalid
     assert ws(0, F32, 100, 5000, 1024, 1) == 3 * 100 * 1024 * 4   # 2048-column strips
-    # FP32 on the VALU path (k <= 16): 1024-column strips at every k; the matrix-core
-    # path (FP32, k > 16) uses 2048-column strips
-    assert ws(0, F32, 4096, 32768, 16, 1) == 32 * 4096 * 16 * 4
+    # FP32 on the VALU path (k <= 8): 4096-column strips at every k; the matrix-core
+    # path (FP32, k > 8) uses 2048-column strips
+    assert ws(0, F32, 4096, 32768, 8, 1) == 8 * 4096 * 8 * 4
+    assert ws(0, F32, 4096, 32768, 9, 1) == 16 * 4096 * 9 * 4
     assert ws(0, F32, 4096, 32768, 17, 1) == 16 * 4096 * 17 * 4
-    assert sk.sketch_strip_width(F32, 5) == 1024 and sk.sketch_strip_width(F32, 9) == 1024
-    assert sk.sketch_strip_width(F32, 17) == 2048
-    # FP8 at every k and BF16 past 16 columns: BF16 matrix cores, 4096-column strips
-    assert sk.sketch_strip_width(BF16, 5) == 2048 and sk.sketch_strip_width(FP8, 4) == 4096
-    assert sk.sketch_strip_width(BF16, 17) == 4096 and sk.sketch_strip_width(FP8, 256) == 4096
+    assert sk.sketch_strip_width(F32, 5) == 4096 and sk.sketch_strip_width(F32, 8) == 4096
+    assert sk.sketch_strip_width(F32, 9) == 2048 and sk.sketch_strip_width(F32, 17) == 2048
+    # FP8 at every k and BF16 past 8 columns: BF16 matrix cores, 4096-column strips
+    assert sk.sketch_strip_width(BF16, 5) == 4096 and sk.sketch_strip_width(FP8, 4) == 4096
+    assert sk.sketch_strip_width(BF16, 9) == 4096 and sk.sketch_strip_width(FP8, 256) == 4096
     # column-major A (op 2): 1024-column strips on the VALU path (k <= 16), the
     # matrix-core strips of 2048 columns past 16, as the row-major matrix-core call
     assert ws(2, F32, 300, 5000, 5, 1) == 5 * 300 * 5 * 4
@@ -270,11 +271,12 @@ def test_request_footprint_rule():
         return r
 
     fp = sv.sk_request_footprint
-    assert fp(req()) == 4 * 512 * 5 * 4                       # 4 strips of 1024 columns
-    assert fp(req(n=1000, lda=1000)) == 0                     # one strip: no partials
+    assert fp(req(n=16384, lda=16384)) == 4 * 512 * 5 * 4     # 4 strips of 4096 columns
+    assert fp(req()) == 0                                     # one strip: no partials
     assert fp(req(n=1000, lda=1000, m=3, k=1, ldy=1)) == 0
     assert fp(req(k=64, ldy=64)) == 2 * 512 * 64 * 4          # matrix core: 2048-column strips
-    assert fp(req(a_source=sv.SK_SRC_SYNTH, A=None)) == 512 * 4096 * 4 + 4 * 512 * 5 * 4
+    assert fp(req(a_source=sv.SK_SRC_SYNTH, A=None, n=16384, lda=16384)) == (
+        512 * 16384 * 4 + 4 * 512 * 5 * 4)
     # staged rows padded to 16 bytes, each part rounded to 256 bytes
     assert fp(req(a_source=sv.SK_SRC_HOST, n=1001, lda=1001, m=3, k=1, ldy=1)) == 12288 + 0
     assert fp(req(a_source=sv.SK_SRC_HOST, n=1001, lda=1001, m=1, k=1, ldy=1)) == 4096

@@ -3,10 +3,11 @@
 Bars:
 * the Philox stream and the generated Omega: bit-exact;
 * Y in FP32: element by element within the rounding-error bound of the
-  kernel's summation (VALU path, k <= 16: chains of at most 64 FP32 products
-  per lane, a 4-level lane tree, FP64 strip sums, one final rounding):
+  kernel's summation (VALU path, k <= 8: chains of 16 FP32 products per lane
+  and 1024-column chunk, a 6-level lane tree, 4 chunk sums per 4096-column
+  strip, FP64 strip sums, one final rounding):
       |Y - Y_ref| <= 80 u sum_j |A_ij Omega_jc| + u |Y_ref|,   u = 2^-24,
-  (matrix-core path, k > 16: a 2048-product chain, 2052 u instead of 80 u),
+  (matrix-core path, k > 8: a 2048-product chain, 2052 u instead of 80 u),
   and the relative Frobenius error <= 1e-5;
 * special cases with exact answers (identity, selection, zero, power-of-two
   scaling) and the layout invariants: bitwise.
@@ -42,9 +43,9 @@ def to_dev(x: np.ndarray) -> torch.Tensor:
 
 def chain(k: int) -> int:
     """Longest FP32 summation chain (+ tree depth) of the kernel that serves width k
-    for FP32 A: at most 16 products per lane + 6 lane levels on the VALU path
-    (k <= 16; bound kept at 80), 2048 + 4 on the matrix-core path (k > 16)."""
-    return 80 if k <= 16 else 2052
+    for FP32 A: 16 products per lane + 6 lane levels + 3 chunk sums on the VALU
+    path (k <= 8; bound kept at 80), 2048 + 4 on the matrix-core path (k > 8)."""
+    return 80 if k <= 8 else 2052
 
 
 def check_fp32(Y: torch.Tensor, A: np.ndarray, seed, row0, col0, k, rel=1e-5):
@@ -221,7 +222,7 @@ def test_reduce_matches_oracle_ragged_blocks():
 def test_reduce_equals_row_layout_bitwise():
     """1Dred (column blocks, device sum) == 1Dnored (row blocks) when the blocks
     are whole strips: same FP32 strip partials, same FP64 order."""
-    m, n, P, k = 512, 8192, 4, 5
+    m, n, P, k = 512, 4 * 4096, 4, 5
     Ad = to_dev(normal_matrix(m, n, seed=13))
     w = n // P
     Yred = sk.sketch_gen_matmul_reduce([Ad[:, b * w:(b + 1) * w] for b in range(P)],

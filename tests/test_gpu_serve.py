@@ -111,7 +111,7 @@ def test_sixty_served_requests_against_oracle():
         ref = oracle.gen_matmul(A, r["seed_omega"], row0, 0, k)
         Om = oracle.omega_block(r["seed_omega"], row0, r["n"], 0, k)
         mag = oracle.matmul(np.abs(A), np.abs(Om))
-        c = 80 if k <= 16 else 2052
+        c = 80 if k <= 8 else 2052
         assert (np.abs(got - ref) <= c * U * mag + U * np.abs(ref)).all(), r
         assert oracle.rel_fro(got, ref) <= 1e-5, r
         classes.add(k)
@@ -145,11 +145,11 @@ def test_host_and_synthetic_sources():
 
 
 def test_budget_admission_and_rejection():
-    m, n, k = 512, 4096, 5
+    m, n, k = 512, 16384, 5
     As = [dev_matrix(m, n, seed=40 + i)[1] for i in range(8)]
     req0 = sv.make_request(A=As[0], k=k, seed=1, Y=torch.empty((m, k), device=DEV))
     fp = sv.sk_request_footprint(req0)
-    assert fp == 4 * m * k * 4                   # 4 strips of 1024 columns, FP32 partials
+    assert fp == 4 * m * k * 4                   # 4 strips of 4096 columns, FP32 partials
     budget = 2 * fp + fp // 2                    # room for two at a time
     Ys = [torch.empty((m, k), device=DEV) for _ in As]
     torch.cuda.synchronize()
