@@ -52,6 +52,57 @@ def measured_traffic(n_row, n_col):
         return None
     pl = rec["per_launch"]
     return (n_row * pl["row"]["traffic_bytes"] + n_col * pl["col"]["traffic_bytes"]) / (n_row + n_col)
+def write_traffic_record(fetch_csv, write_csv):
+    """Per-launch HBM bytes of the streaming kernel from two rocprofv3 counter
+    passes (FETCH_SIZE, WRITE_SIZE; counter_collection CSVs) over
+    `bench.py --copy-calibration`: each counter is scaled by what it reads for
+    the plain 1 GiB copy of that run, and the kernel's dispatches are split into
+    row-share and column-layout launches by their A bytes.  Writes
+    profiles/traffic_k_gemm_stream_k5_f32.json with the sources' hash."""
+    import csv
+    import hashlib
+
+    def per_dispatch(path, counter):
+        vals, names = {}, {}
+        with open(path) as f:
+            for row in csv.DictReader(f):
+                if row.get("Counter_Name") != counter:
+                    continue
+                d = row["Dispatch_Id"]
+                vals[d] = vals.get(d, 0.0) + float(row["Counter_Value"])
+                names[d] = row["Kernel_Name"]
+        return vals, names
+
+    out = {"kernel": "k_gemm_stream<5, f32, generated>"}
+    per = {}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        vals, names = per_dispatch(path, counter)
+        copy = [v for d, v in vals.items() if "copyBuffer" in names[d]]
+        # the copy reads and writes exactly 1 GiB (1048576 KiB)
+        scale = 1048576.0 / (sorted(copy)[len(copy) // 2])
+        out["fetch_scale" if counter == "FETCH_SIZE" else "write_scale"] = scale
+        for d, v in vals.items():
+            if "k_gemm_stream<5, 0, true>" in names[d]:
+                per.setdefault(d, {})[counter] = v * scale * 1024.0
+    row = [v for v in per.values() if v["FETCH_SIZE"] < 2e9]
+    col = [v for v in per.values() if v["FETCH_SIZE"] >= 2e9]
+    out["per_launch"] = {}
+    for kind, items, alg in (("row", row, 4096 * 32768 * 4), ("col", col, 32768 * 32768 * 4)):
+        fb = sum(x["FETCH_SIZE"] for x in items) / len(items)
+        wb = sum(x["WRITE_SIZE"] for x in items) / len(items)
+        out["per_launch"][kind] = {"dispatches": len(items), "fetch_bytes": round(fb),
+                                   "write_bytes": round(wb), "algorithmic_bytes": alg,
+                                   "traffic_bytes": round(fb + wb),
+                                   "fetch_over_algorithmic": fb / alg}
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    out["kernel_sources_sha256"] = h.hexdigest()
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
+
+
 METRIC = "A-stream GB/s (% HBM peak) for Y=A·Ω(seed) at k=5; p50/p99 latency served"
 
 
@@ -80,6 +131,10 @@ def parse():
                    help="also run a plain 1 GiB device copy (known traffic) for counter scaling")
     p.add_argument("--cpu-seconds", type=float, default=10.0,
                    help="minimum duration of the oracle's timed run")
+    p.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                   help="write profiles/traffic_k_gemm_stream_k5_f32.json from two rocprofv3 "
+                        "counter_collection CSVs (FETCH_SIZE, WRITE_SIZE) of a "
+                        "--copy-calibration run, and exit")
     p.add_argument("--share-streams", type=int, default=2,
                    help="streams the P independent shares of a step are spread over (the P "
                         "processes of the layout run concurrently); 1 = one after another")
@@ -482,6 +537,8 @@ def run_serve(args, torch, quiet=False):
 
 def main():
     args = parse()
+    if args.traffic_from:
+        return write_traffic_record(*args.traffic_from)
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)

@@ -712,7 +712,9 @@ hipError_t dispatch_k(int kc, const KArgs& a, dim3 grid, hipStream_t s, const Tr
     case 4: return launch_k<4, ADT, GEN>(a, grid, s, tr);
     case 5: return launch_k<5, ADT, GEN>(a, grid, s, tr);
     case 6: return launch_k<6, ADT, GEN>(a, grid, s, tr);
-    default: return launch_k<8, ADT, GEN>(a, grid, s, tr);
+    default:
+        if constexpr (ADT == 0) return launch_k<8, ADT, GEN>(a, grid, s, tr);
+        return hipErrorInvalidValue;   // BF16 past 6 columns runs on the matrix cores
     }
 }
 
@@ -862,7 +864,9 @@ hipError_t run_batch_k(int kclass, const BatchArgs& a, int grid, hipStream_t s) 
     case 4: return run_batch<4, ADT>(a, grid, s);
     case 5: return run_batch<5, ADT>(a, grid, s);
     case 6: return run_batch<6, ADT>(a, grid, s);
-    case 8: return run_batch<8, ADT>(a, grid, s);
+    case 8:
+        if constexpr (ADT == 0) return run_batch<8, ADT>(a, grid, s);
+        return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
     }
 }

@@ -46,20 +46,22 @@ constexpr int stream_max_rows(int /*kclass*/) { return 16 * 8 * kStreamWaves; }
 // hold 8 rows of k accumulators.  Its strips are 2048 columns.
 constexpr int kMfmaStrip = 2048;
 constexpr int kMfmaRows = 512;     // rows of a matrix-core tile
-constexpr int kStreamMaxK = 8;     // widest sketch of the streaming kernel
+constexpr int kStreamMaxK = 8;     // widest sketch of the streaming kernel (FP32 A)
+constexpr int kStreamMaxKBf16 = 6; // ... for BF16 A (its unpacked elements take 32 more registers)
 constexpr int kMfmaMinK = kStreamMaxK + 1;
 constexpr bool use_mfma(int adtype, int64_t k) { return adtype == 0 && k >= kMfmaMinK; }
 
 // Low-precision A on the BF16 matrix cores: FP8 at every k (on the VALU path
 // its conversions and 5 FMAs per byte cap k = 5 at 2.6 TB/s, against 3.2 TB/s
-// here), BF16 from k = 9 on (at k = 5 both paths measured the same speed, and
-// the VALU path sums with FP32 Omega: 1e-7 against 2.5e-6 relative arithmetic
-// error).  Strips of 4096 columns.
+// here), BF16 from k = 7 on, where the streaming kernel's registers no longer
+// hold 8 rows of unpacked BF16 and k accumulators (at k = 5 both paths
+// measured the same speed, and the VALU path sums with FP32 Omega: 1e-7
+// against 2.5e-6 relative arithmetic error).  Strips of 4096 columns.
 constexpr int kLpStrip = 4096;
 constexpr int kLpBatchWaves = 8;                  // waves per tile in batched launches
 constexpr int kLpBatchRows = 64 * kLpBatchWaves;  // rows per tile in batched launches
 constexpr bool use_mfma_lp(int adtype, int64_t k) {
-    return adtype == 2 || (adtype == 1 && k > kStreamMaxK);
+    return adtype == 2 || (adtype == 1 && k > kStreamMaxKBf16);
 }
 
 // Strip width used for a sketch of width k with A stored as adtype.

@@ -106,10 +106,12 @@ def test_noalloc_rejects(kw, expect):
 
 
 def test_noalloc_rejects_calls_beyond_its_scratch():
-    # the largest m whose strip partials fit, and one row more (checked on the host)
-    per_row = sk.sketch_workspace_size(0, F32, 1, 32768, 5, 1)
-    m_max = NOALLOC_BYTES // per_row
-    assert sk.sketch_workspace_size(0, F32, m_max + 1, 32768, 5, 1) > NOALLOC_BYTES
+    # the largest m whose workspace fits, and one row more (checked on the host)
+    ws = sk.sketch_workspace_size
+    per_row = ws(0, F32, 2, 32768, 5, 1) - ws(0, F32, 1, 32768, 5, 1)
+    base = ws(0, F32, 1, 32768, 5, 1) - per_row
+    m_max = (NOALLOC_BYTES - base) // per_row
+    assert ws(0, F32, m_max, 32768, 5, 1) <= NOALLOC_BYTES < ws(0, F32, m_max + 1, 32768, 5, 1)
     assert gm_noalloc(m=m_max + 1, n=32768, lda=32768) == -11
     assert gm_noalloc(m=1 << 20, n=1 << 15, lda=1 << 15, k=64, ldy=64) == -11
     assert sk.sketch_status_string(-11) != "unknown status"
@@ -220,7 +222,7 @@ def test_column_major_and_second_product_reject_on_host():
 
 def test_workspace_size_rules():
     ws = sk.sketch_workspace_size
-    assert ws(0, F32, 4096, 4096, 5, 1) == 0          # one strip: written directly, no partials
+    assert ws(0, F32, 4096, 4096, 5, 1) == 0          # one strip: Y written directly, no partials
     a = ws(0, F32, 4096, 32768, 5, 1)
     assert a == 8 * 4096 * 5 * 4                        # 8 strips of 4096 columns
     b = ws(1, F32, 32768, 32768, 5, 8)

@@ -5,7 +5,7 @@ Omega here is NOT the generated one: an arbitrary FP32 matrix held in a strided
 device buffer (ldo > k, a column offset), so a wrong ldo, column base or row
 index in the kernels' stored-operand branches shows.  Every kernel family runs:
 FP32 A on the VALU path (k <= 8) and the FP32 matrix cores (k > 8, one and
-several column blocks), BF16 A (VALU for k <= 8, BF16 matrix cores above),
+several column blocks), BF16 A (VALU for k <= 6, BF16 matrix cores above),
 FP8 A with per-128-row scales (BF16 matrix cores).
 
 Bars (u = 2^-24): the reference is oracle.matmul on the exactly dequantised A
@@ -41,7 +41,7 @@ def dev_f32(x):
 def chain(kind, k):
     if kind == "f32":
         return 80 if k <= 8 else 2052
-    if kind == "bf16" and k <= 8:
+    if kind == "bf16" and k <= 6:
         return 80
     return 4096 + 4 + 256
 

@@ -7,7 +7,7 @@ library's static scratch left over from the first call does not leak into the
 second result.  Cases: the streaming kernel (FP32, k = 5, several strips and a
 ragged tail), the matrix-core kernel (FP32, k = 40), the low-precision kernel
 (BF16, k = 64) and one call whose partials fill the scratch up to its limit
-(16384 x 32768 at k = 16: 32 strips x 16384 rows x 16 FP32 partials = 32 MiB).
+(8192 x 32768 at k = 64: 16 strips x 8192 rows x 64 FP32 partials = 32 MiB).
 """
 import ctypes
 
@@ -75,8 +75,8 @@ def test_noalloc_low_precision_kernel_two_calls():
 
 def test_noalloc_full_scratch_then_smaller():
     L = sk.lib()
-    n, k = 32768, 16
-    per_row = L.sketch_workspace_size(0, 0, 1, n, k, 1)
+    n, k = 32768, 64                       # matrix cores: 16 strips of 2048 columns
+    per_row = L.sketch_workspace_size(0, 0, 2, n, k, 1) - L.sketch_workspace_size(0, 0, 1, n, k, 1)
     m = SCRATCH // per_row
     assert L.sketch_workspace_size(0, 0, m, n, k, 1) <= SCRATCH
     _pair([((m, n), 0), ((1000, 5000), 11)], k, torch.float32)
