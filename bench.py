@@ -174,6 +174,58 @@ def cpu_baseline(A, P, k, seed, target_s):
                       f"{N}x{N} A, k={k}) repeated {reps}x, {dt:.1f} s wall"}
 
 
+def _oracle_time(fn, target_s):
+    """Shortest of repeated calls of fn within about target_s seconds (at least 2 calls)."""
+    best, reps, t0 = float("inf"), 0, time.perf_counter()
+    while reps < 2 or (time.perf_counter() - t0 < target_s and reps < 1000):
+        t1 = time.perf_counter()
+        fn()
+        best = min(best, time.perf_counter() - t1)
+        reps += 1
+    return best
+
+
+def _oracle_fit(call, m, target_s, r_lo=64, r_hi=256):
+    """Oracle time of one call over m rows, from calls over r_lo and r_hi rows: the oracle
+    generates the whole Omega block once per call and then does rows x n x k work, so its
+    time is a + b * rows; the line through the two samples is evaluated at m."""
+    if m <= r_hi:
+        return _oracle_time(lambda: call(m), target_s)
+    t_lo = _oracle_time(lambda: call(r_lo), target_s / 2)
+    t_hi = _oracle_time(lambda: call(r_hi), target_s / 2)
+    return t_lo + (t_hi - t_lo) * (m - r_lo) / (r_hi - r_lo)
+
+
+def oracle_rows(kind, shapes, ks, target_s, r_lo=64, r_hi=256):
+    """CPU oracle rate on each workload shape, from row samples (r_lo and r_hi rows of a
+    host N(0,1) A: FP32, or its BF16 / FP8 codes) extrapolated linearly to all m rows."""
+    import oracle
+    from sketch_inputs import normal_matrix
+
+    out = []
+    for (m, n) in shapes:
+        Ah = normal_matrix(r_hi, n, seed=0)
+        if kind == "f32":
+            Aq, sc, esz = Ah, None, 4
+        elif kind == "bf16":
+            Aq, sc, esz = oracle.bf16_encode(Ah), None, 2
+        else:
+            (Aq, sc), esz = oracle.quantize_fp8_rows128(Ah), 1
+        for k in ks:
+            if kind == "f32":
+                call = lambda r: oracle.gen_matmul(Aq[:r], 1, 0, 0, k)
+            else:
+                call = lambda r: oracle.gen_matmul_q(Aq[:r], kind, sc, 1, 0, 0, k)
+            t0 = time.perf_counter()
+            t = _oracle_fit(call, m, target_s, r_lo, r_hi)
+            out.append({"a_dtype": kind, "k": k, "value": round(m * n * esz / t / 1e9, 3),
+                        "unit": "GB/s", "call_s": round(t, 3), "cores": oracle.num_threads(),
+                        "kind": "oracle",
+                        "sample": f"{m} x {n} call time from {r_lo}- and {r_hi}-row calls "
+                                  f"(time linear in rows), {time.perf_counter() - t0:.1f} s wall"})
+    return out
+
+
 def _timeit(torch, stream, fn, reps, warmup=2):
     """Median and minimum of reps timed calls (HIP events on the launch stream), in ms."""
     for _ in range(warmup):
@@ -235,6 +287,8 @@ def run_ksweep(args):
                      "stored Omega", "unit": "ms", "n_gpus": 1, "steps": args.steps,
            "higher_is_better": False, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "A 65536x16384 fp32 N(0,1), k in {5,16,64,256}"}, "rows": rows}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = oracle_rows("f32", [(m, n)], (5, 16, 64, 256), args.cpu_seconds / 4)
     print(json.dumps(out), flush=True)
 
 
@@ -277,6 +331,9 @@ def run_precision(args):
            "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "higher_is_better": True,
            "dtype": "bf16/fp8 storage, f32 accumulate", "data": "synthetic",
            "config": {"workload": "A 32768x32768 N(0,1), k in {5, 64}"}, "rows": rows}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = [x for kind in ("bf16", "fp8")
+                               for x in oracle_rows(kind, [(N, N)], (5, 64), args.cpu_seconds / 4)]
     print(json.dumps(out), flush=True)
 
 
@@ -531,8 +588,33 @@ def run_serve(args, torch, quiet=False):
                                "server vs back-to-back sketch_gen_matmul calls on one stream"},
     }
     if not quiet:
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"] = oracle_requests(base, args.cpu_seconds)
         print(json.dumps(out), flush=True)
     return out
+
+
+def oracle_requests(reqs, target_s, r_lo=64, r_hi=256):
+    """CPU oracle on the served stream: requests in arrival order until about target_s
+    seconds; each request's time comes from r_lo- and r_hi-row calls on a host N(0,1) A of
+    its n, extrapolated linearly to its m rows; requests/s and GB/s of A over them."""
+    import oracle
+    from sketch_inputs import normal_matrix
+
+    pool = normal_matrix(r_hi, max(r["n"] for r in reqs), seed=0)
+    est, nbytes, done = 0.0, 0, 0
+    t0 = time.perf_counter()
+    for r in reqs:
+        call = lambda rows: oracle.gen_matmul(pool[:rows, :r["n"]], r["seed_omega"], 0, 0, r["k"])
+        est += _oracle_fit(call, r["m"], 0.0, r_lo, r_hi)
+        nbytes += 4 * r["m"] * r["n"]
+        done += 1
+        if time.perf_counter() - t0 >= target_s:
+            break
+    return {"value": round(done / est, 2), "unit": "req/s", "GBps": round(nbytes / est / 1e9, 3),
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"first {done} requests of the stream, each from {r_lo}- and {r_hi}-row "
+                      f"calls extrapolated to m rows ({time.perf_counter() - t0:.1f} s wall)"}
 
 
 def main():
