@@ -116,7 +116,7 @@ def parse():
                    choices=["shares", "ksweep", "precision", "serve", "dists", "colmajor",
                             "nystrom"],
                    help="shares: the headline step (default); ksweep: 65536x16384, k in "
-                        "{5,16,64,256}, generated vs stored Omega; precision: BF16 / FP8 A; "
+                        "{5,16,64,256,1000}, generated vs stored Omega; precision: BF16 / FP8 A; "
                         "serve: Poisson stream of uneven requests through the request server; "
                         "dists: normal / uniform / Rademacher Omega on 32768x32768; "
                         "colmajor: column-major A, transposed form, C = Omega^T B; "
@@ -245,7 +245,7 @@ def _timeit(torch, stream, fn, reps, warmup=2):
 
 
 def run_ksweep(args):
-    """65536 x 16384 FP32 A, k in {5, 16, 64, 256}: the generated operand (one call) against
+    """65536 x 16384 FP32 A, k in {5, 16, 64, 256, 1000}: the generated operand (one call) against
     the stored operand (Omega materialised in HBM by sketch_gen_omega, then read by
     sketch_matmul_omega), i.e. Gen vs Comm of Sec. 6.3 on one device."""
     import torch
@@ -258,7 +258,7 @@ def run_ksweep(args):
     m, n = 65536, 16384
     A = normal_matrix_device(m, n, seed=0, device=dev)
     rows = []
-    for k in (5, 16, 64, 256):
+    for k in (5, 16, 64, 256, 1000):
         Y = torch.empty((m, k), device=dev)
         Om = torch.empty((n, k), device=dev)
         t_gen, t_gen_min = _timeit(torch, stream, lambda: sk.sketch_gen_matmul(A, 1, k, Y=Y,
@@ -270,7 +270,7 @@ def run_ksweep(args):
                           args.steps)
         bytes_a = m * n * 4
         flops = 2 * m * n * k
-        kern = "matrix cores (v_mfma_f32_16x16x4f32)" if k > 16 else "VALU FMA"
+        kern = "matrix cores (v_mfma_f32_16x16x4f32)" if k > 8 else "VALU FMA"
         bound = "hbm" if k <= 16 else "mfma_fp32"
         peak = HBM_PEAK_GBPS if bound == "hbm" else 157.3
         achieved = bytes_a / (t_gen * 1e-3) / 1e9 if bound == "hbm" else flops / (t_gen * 1e-3) / 1e12
@@ -286,7 +286,7 @@ def run_ksweep(args):
     out = {"metric": "Y=A*Omega(seed) time per call, 65536x16384 FP32 A, k sweep; generated vs "
                      "stored Omega", "unit": "ms", "n_gpus": 1, "steps": args.steps,
            "higher_is_better": False, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": "A 65536x16384 fp32 N(0,1), k in {5,16,64,256}"}, "rows": rows}
+           "config": {"workload": "A 65536x16384 fp32 N(0,1), k in {5,16,64,256,1000}"}, "rows": rows}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = oracle_rows("f32", [(m, n)], (5, 16, 64, 256), args.cpu_seconds / 4)
     print(json.dumps(out), flush=True)
@@ -318,7 +318,7 @@ def run_precision(args):
             Y = torch.empty((N, k), device=dev)
             t, _ = _timeit(torch, stream, lambda: sk.sketch_gen_matmul(Aq, 1, k, Y=Y, a_scales=sc,
                                                                        stream=stream), args.steps)
-            on_mc = kind == "fp8" or k > 16
+            on_mc = kind == "fp8" or k > 6
             flops = 2 * N * N * 16 * -(-k // 16) * 2      # hi + lo BF16 terms, padded N-tiles
             rows.append({"a_dtype": kind, "k": k, "ms": round(t, 4),
                          "kernel": ("BF16 matrix cores (v_mfma_f32_16x16x32_bf16, Omega hi+lo)"
@@ -439,16 +439,22 @@ def run_nystrom(args):
                              args.steps)
             t_c, _ = _timeit(torch, stream, lambda: ny.sketch_gen_tmatmul(B, 11, r, C=C, stream=stream),
                              args.steps)
-            t_p, _ = _timeit(torch, stream, lambda: ny.core_pinv(C, ny.default_tol(r)), 3)
-            err = ny.relative_error(A, B, Cp)
+            t_p, _ = _timeit(torch, stream, lambda: ny.core_pinv(C, ny.PAPER_TOL, stream=stream), 3)
+            _, info = ny.core_pinv(C, ny.PAPER_TOL, stream=stream)
+            t_e, _ = _timeit(torch, stream, lambda: ny.sketch_nystrom_error(A, B, Cp, stream=stream),
+                             1, warmup=1)
+            err = ny.relative_error(A, B, Cp, stream=stream)
+            sweeps, conv = (int(x) for x in info.cpu())
             rows.append({"kernel": kind, "r": r, "rel_fro_error": float(f"{err:.3e}"),
                          "B_ms": round(t_b, 4), "C_ms": round(t_c, 4), "pinv_ms": round(t_p, 4),
+                         "pinv_sweeps": sweeps, "pinv_converged": bool(conv),
+                         "error_eval_ms": round(t_e, 3),
                          "B_A_GBps": round(n * n * 4 / (t_b * 1e-3) / 1e9, 1)})
         del A
         torch.cuda.empty_cache()
     out = {"metric": "Nystrom relative Frobenius error and step times, n = 32768",
            "unit": "ms", "n_gpus": 1, "steps": args.steps, "higher_is_better": False,
-           "dtype": "f32 products, f64 core pseudo-inverse", "data": "synthetic",
+           "dtype": "f32 products, f64 core pseudo-inverse (tolerance 1e-12)", "data": "synthetic",
            "config": {"workload": "synthetic PSD kernels 32768 x 32768 (linear: data of rank 40; "
                                   "rbf: sigma = ||X||/sqrt(n)), r in {64, 256}"},
            "rows": rows}

@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define SKETCH_ABI_VERSION 5
+#define SKETCH_ABI_VERSION 6
 
 enum sk_status {
     SK_OK = 0,
@@ -305,6 +305,63 @@ int sketch_normal_raw(const uint32_t* words, float* out, int64_t N, void* stream
  */
 int sketch_quantize(const float* A, int64_t m, int64_t n, int64_t lda, int dst_dtype, void* Aq,
                     int64_t ldq, float* scales, void* stream);
+
+/*
+ * Nystrom approximation (Sec. 5, Alg. 2): for a symmetric positive semidefinite
+ * n x n A, B = A Omega (sketch_gen_matmul) and the core C = Omega^T B
+ * (sketch_gen_tmatmul) give A~ = B C^+ B^T.  The three calls below finish it
+ * on the device, in FP64.  Unlike the product calls they run several kernels;
+ * they still only enqueue work.
+ *
+ * sketch_core_pinv: the pseudo-inverse of the core, as the paper forms it
+ * (eigenvalues below a relative tolerance dropped; Sec. 6.2 uses 1e-12):
+ *   S = (C + C^T) / 2 = V diag(lambda) V^T by a parallel block Jacobi
+ *   eigensolver (cyclic sweeps of 2x2 rotations over 16-row block pairs, stopped
+ *   when the off-diagonal Frobenius norm of the rotated S is at most
+ *   8 Rp 2^-53 ||S||_F, Rp = r rounded up to a multiple of 32, or after
+ *   max_sweeps sweeps), then
+ *   Cp = V diag(mu) V^T, mu_i = 1 / lambda_i if |lambda_i| > tol max_j |lambda_j|,
+ *   else 0.
+ *   C     device, r x r row-major, leading dim ldc >= r, storage c_dtype
+ *         (SK_Y_F32 or SK_Y_F64); only read.
+ *   r     0 <= r <= 1024 (r = 0: nothing is done).
+ *   tol   relative eigenvalue cut, 0 <= tol <= 1.
+ *   max_sweeps  1 .. 100 (about 6 to 14 are needed for r <= 1024).
+ *   Cp    device, r x r FP64 row-major, leading dim ldcp >= r; exactly
+ *         symmetric.
+ *   eigvals  device FP64 array of r (the lambda_i, unsorted) or NULL.
+ *   info  device int32[2] or NULL: (sweeps run, 1 if converged else 0).
+ *   workspace  device, at least sketch_core_pinv_workspace(r) bytes
+ *         (16-byte aligned); its contents on entry do not matter.
+ *   Errors: SK_EDTYPE, SK_EINVAL (sizes, tol, max_sweeps, NULL buffers),
+ *   SK_EALIGN, SK_EWORKSPACE, SK_EHIP.
+ */
+size_t sketch_core_pinv_workspace(int64_t r);
+int sketch_core_pinv(const void* C, int c_dtype, int64_t r, int64_t ldc, double tol,
+                     int max_sweeps, double* Cp, int64_t ldcp, double* eigvals, int32_t* info,
+                     void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * Reconstruction from the factors (Table 2's relative error and rows of A~):
+ *   B   device, n x r FP32 row-major, leading dim ldb >= r (1 <= r <= 1024);
+ *   Cp  device, r x r FP64 (symmetric, e.g. from sketch_core_pinv), ldcp >= r.
+ *   W = B Cp is formed in FP64 in the workspace, then A~(i, j) = W(i, :) B(j, :)^T,
+ *   every sum in FP64 in a fixed order.
+ * sketch_nystrom_error: sums (device FP64[3]) = (||A - A~||_F^2, ||A||_F^2,
+ *   their ratio's square root, 0 if ||A|| = 0) for A device n x n FP32
+ *   row-major, lda >= n.  n = 0: nothing is written.
+ * sketch_nystrom_rows: out (device FP64, mr x n row-major, ldo >= n) = rows
+ *   [row0, row0 + mr) of A~, 0 <= row0 <= n - mr.
+ * workspace: sketch_nystrom_workspace(n, r) bytes (both calls), 16-byte
+ * aligned.  n is limited to 64 * 65535 (SK_EUNSUPPORTED beyond).
+ */
+size_t sketch_nystrom_workspace(int64_t n, int64_t r);
+int sketch_nystrom_error(const float* A, int64_t n, int64_t lda, const float* B, int64_t r,
+                         int64_t ldb, const double* Cp, int64_t ldcp, double* sums,
+                         void* workspace, size_t workspace_bytes, void* stream);
+int sketch_nystrom_rows(const float* B, int64_t n, int64_t r, int64_t ldb, const double* Cp,
+                        int64_t ldcp, int64_t row0, int64_t mr, double* out, int64_t ldo,
+                        void* workspace, size_t workspace_bytes, void* stream);
 
 #ifdef __cplusplus
 }

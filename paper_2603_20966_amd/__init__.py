@@ -85,12 +85,21 @@ def lib() -> ctypes.CDLL:
         L.sketch_normal_raw.argtypes = [P, P, i64, P]
         L.sketch_quantize.argtypes = [P, i64, i64, i64, i32, P, i64, P, P]
         L.sketch_trace_events.argtypes = [P, P, P]
+        L.sketch_core_pinv_workspace.argtypes = [i64]
+        L.sketch_core_pinv_workspace.restype = sz
+        L.sketch_core_pinv.argtypes = [P, i32, i64, i64, ctypes.c_double, i32, P, i64, P, P, P, sz,
+                                       P]
+        L.sketch_nystrom_workspace.argtypes = [i64, i64]
+        L.sketch_nystrom_workspace.restype = sz
+        L.sketch_nystrom_error.argtypes = [P, i64, i64, P, i64, i64, P, i64, P, P, sz, P]
+        L.sketch_nystrom_rows.argtypes = [P, i64, i64, i64, P, i64, i64, i64, P, i64, P, sz, P]
         for f in ("sketch_gen_matmul", "sketch_gen_matmul_noalloc", "sketch_gen_matmul_reduce", "sketch_gen_matmul_dist",
                   "sketch_gen_matmul_reduce_dist", "sketch_gen_omega_dist",
                   "sketch_gen_matmul_cm", "sketch_gen_tmatmul",
                   "sketch_gen_omega", "sketch_matmul_omega", "sketch_philox_raw",
                   "sketch_normal_raw",
-                  "sketch_quantize", "sketch_trace_events"):
+                  "sketch_quantize", "sketch_trace_events", "sketch_core_pinv",
+                  "sketch_nystrom_error", "sketch_nystrom_rows"):
             getattr(L, f).restype = i32
         _lib = L
         return L
@@ -366,6 +375,81 @@ def sketch_gen_tmatmul(B: torch.Tensor, seed: int, k: int, *, omega_row0: int = 
     return C
 
 
+def sketch_core_pinv(C: torch.Tensor, tol: float = 1e-12, *, max_sweeps: int = 16,
+                     Cp: torch.Tensor | None = None, eigvals: bool = False,
+                     workspace: torch.Tensor | None = None, stream=None):
+    """FP64 pseudo-inverse of the symmetric part of the r x r core C (FP32 or FP64,
+    row-major), eigenvalues with |lambda| <= tol * max|lambda| dropped (Sec. 5, Alg. 2;
+    tolerance of Sec. 6.2).  Returns (Cp, info) or (Cp, info, eigenvalues); info is a
+    device int32 pair (sweeps run, converged)."""
+    if C.dim() != 2 or C.shape[0] != C.shape[1]:
+        raise ValueError("C must be square")
+    r = int(C.shape[0])
+    cdt = {torch.float32: SK_Y_F32, torch.float64: SK_Y_F64}.get(C.dtype)
+    if cdt is None:
+        raise TypeError("C must be float32 or float64")
+    ldc = _ld(C, "C") if r else 1
+    if Cp is None:
+        Cp = torch.empty((r, r), dtype=torch.float64, device=C.device)
+    ldcp = _ld(Cp, "Cp") if r else 1
+    info = torch.zeros(2, dtype=torch.int32, device=C.device)
+    eig = torch.empty(r, dtype=torch.float64, device=C.device) if eigvals else None
+    st = _stream(stream, C.device)
+    need = int(lib().sketch_core_pinv_workspace(r))
+    if workspace is not None:
+        wsp, wsb = _ptr(workspace), workspace.numel() * workspace.element_size()
+    else:
+        wsp, wsb = workspace_for(need, C.device, st)
+    _check(lib().sketch_core_pinv(_ptr(C), cdt, r, ldc, float(tol), int(max_sweeps), _ptr(Cp), ldcp,
+                                  _ptr(eig), _ptr(info), wsp, wsb, st), "sketch_core_pinv")
+    return (Cp, info, eig) if eigvals else (Cp, info)
+
+
+def _nystrom_ws(n, r, device, st, workspace):
+    need = int(lib().sketch_nystrom_workspace(n, r))
+    if workspace is not None:
+        return _ptr(workspace), workspace.numel() * workspace.element_size()
+    return workspace_for(need, device, st)
+
+
+def sketch_nystrom_error(A: torch.Tensor, B: torch.Tensor, Cp: torch.Tensor, *,
+                         sums: torch.Tensor | None = None, workspace: torch.Tensor | None = None,
+                         stream=None) -> torch.Tensor:
+    """Device FP64 (||A - B Cp B^T||_F^2, ||A||_F^2, relative error) for an n x n FP32 A,
+    n x r FP32 B and r x r FP64 Cp (Table 2's error of the Nystrom approximation)."""
+    n, r = int(B.shape[0]), int(B.shape[1])
+    if A.dtype != torch.float32 or B.dtype != torch.float32 or Cp.dtype != torch.float64:
+        raise TypeError("A, B float32 and Cp float64")
+    if tuple(A.shape) != (n, n) or tuple(Cp.shape) != (r, r):
+        raise ValueError("A must be n x n and Cp r x r for B n x r")
+    if sums is None:
+        sums = torch.zeros(3, dtype=torch.float64, device=B.device)
+    st = _stream(stream, B.device)
+    wsp, wsb = _nystrom_ws(n, r, B.device, st, workspace)
+    _check(lib().sketch_nystrom_error(_ptr(A), n, _ld(A, "A") if n else 1, _ptr(B), r,
+                                      _ld(B, "B") if n else r, _ptr(Cp), _ld(Cp, "Cp"),
+                                      _ptr(sums), wsp, wsb, st), "sketch_nystrom_error")
+    return sums
+
+
+def sketch_nystrom_rows(B: torch.Tensor, Cp: torch.Tensor, row0: int, mr: int, *,
+                        out: torch.Tensor | None = None, workspace: torch.Tensor | None = None,
+                        stream=None) -> torch.Tensor:
+    """Rows [row0, row0 + mr) of A~ = B Cp B^T (FP64, mr x n)."""
+    n, r = int(B.shape[0]), int(B.shape[1])
+    if B.dtype != torch.float32 or Cp.dtype != torch.float64:
+        raise TypeError("B float32 and Cp float64")
+    if out is None:
+        out = torch.empty((mr, n), dtype=torch.float64, device=B.device)
+    st = _stream(stream, B.device)
+    wsp, wsb = _nystrom_ws(n, r, B.device, st, workspace)
+    _check(lib().sketch_nystrom_rows(_ptr(B), n, r, _ld(B, "B") if n else r, _ptr(Cp),
+                                     _ld(Cp, "Cp"), row0, mr, _ptr(out),
+                                     _ld(out, "out") if out.numel() else max(n, 1), wsp, wsb, st),
+           "sketch_nystrom_rows")
+    return out
+
+
 def sketch_philox_raw(ctr: torch.Tensor, seed: int, *, out: torch.Tensor | None = None,
                       stream=None) -> torch.Tensor:
     """Philox4x32-10 of each row of ctr (N x 4 int32/uint32 device tensor) under key = seed."""
@@ -427,5 +511,5 @@ __all__ = ["sketch_abi_version", "sketch_status_string", "sketch_workspace_size"
            "sketch_gen_matmul_cm",
            "sketch_gen_tmatmul",
            "sketch_gen_omega", "sketch_matmul_omega", "sketch_philox_raw", "sketch_normal_raw",
-           "sketch_quantize",
+           "sketch_quantize", "sketch_core_pinv", "sketch_nystrom_error", "sketch_nystrom_rows",
            "sketch_trace_events", "SketchError", "lib", "LIB_PATH"]

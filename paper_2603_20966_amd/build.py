@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsketch.so")
 SOURCES = ["sk_api.cpp", "sk_serve.cpp", "sk_sched.cpp", "sk_gemm.hip", "sk_mfma.hip", "sk_misc.hip",
-           "sk_cm.hip", "sk_noalloc.hip"]
+           "sk_cm.hip", "sk_noalloc.hip", "sk_nystrom.hip"]
 ARCH = "gfx950"
 
 

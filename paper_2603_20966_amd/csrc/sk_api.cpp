@@ -376,4 +376,69 @@ int sketch_quantize(const float* A, int64_t m, int64_t n, int64_t lda, int dst_d
                                         static_cast<hipStream_t>(stream)));
 }
 
+size_t sketch_core_pinv_workspace(int64_t r) {
+    if (r < 0 || r > sk::kPinvMaxR) return 0;
+    return sk::pinv_workspace_bytes(r);
+}
+
+int sketch_core_pinv(const void* C, int c_dtype, int64_t r, int64_t ldc, double tol,
+                     int max_sweeps, double* Cp, int64_t ldcp, double* eigvals, int32_t* info,
+                     void* workspace, size_t workspace_bytes, void* stream) {
+    if (c_dtype != SK_Y_F32 && c_dtype != SK_Y_F64) return SK_EDTYPE;
+    if (r < 0 || r > sk::kPinvMaxR) return SK_EINVAL;
+    if (!(tol >= 0.0) || tol > 1.0 || max_sweeps < 1 || max_sweeps > 100) return SK_EINVAL;
+    if (r == 0) return SK_OK;
+    if (C == nullptr || Cp == nullptr || ldc < r || ldcp < r) return SK_EINVAL;
+    const uintptr_t cal = c_dtype == SK_Y_F64 ? 7u : 3u;
+    if (((uintptr_t)C & cal) || ((uintptr_t)Cp & 7u) || ((uintptr_t)eigvals & 7u) ||
+        ((uintptr_t)info & 3u))
+        return SK_EALIGN;
+    const int st = check_workspace(sk::pinv_workspace_bytes(r), workspace, workspace_bytes);
+    if (st != SK_OK) return st;
+    return from_hip(sk::launch_core_pinv(C, c_dtype == SK_Y_F64, r, ldc, tol, max_sweeps, Cp, ldcp,
+                                         eigvals, info, workspace,
+                                         static_cast<hipStream_t>(stream)));
+}
+
+size_t sketch_nystrom_workspace(int64_t n, int64_t r) {
+    if (n < 0 || r < 0 || r > sk::kPinvMaxR) return 0;
+    return sk::nystrom_workspace_bytes(n, r);
+}
+
+namespace {
+int check_nystrom(const float* B, int64_t n, int64_t r, int64_t ldb, const double* Cp,
+                  int64_t ldcp, const void* ws, size_t wsb) {
+    if (n < 0 || r < 1 || r > sk::kPinvMaxR) return SK_EINVAL;
+    if (n == 0) return SK_OK;
+    if (B == nullptr || Cp == nullptr || ldb < r || ldcp < r) return SK_EINVAL;
+    if (((uintptr_t)B & 3u) || ((uintptr_t)Cp & 7u)) return SK_EALIGN;
+    if ((n + 63) / 64 > kMaxGridY) return SK_EUNSUPPORTED;
+    return check_workspace(sk::nystrom_workspace_bytes(n, r), ws, wsb);
+}
+}  // namespace
+
+int sketch_nystrom_error(const float* A, int64_t n, int64_t lda, const float* B, int64_t r,
+                         int64_t ldb, const double* Cp, int64_t ldcp, double* sums,
+                         void* workspace, size_t workspace_bytes, void* stream) {
+    int st = check_nystrom(B, n, r, ldb, Cp, ldcp, workspace, workspace_bytes);
+    if (st != SK_OK || n == 0) return st;
+    if (A == nullptr || sums == nullptr || lda < n) return SK_EINVAL;
+    if (((uintptr_t)A & 3u) || ((uintptr_t)sums & 7u)) return SK_EALIGN;
+    return from_hip(sk::launch_nystrom(A, lda, B, n, r, ldb, Cp, ldcp, 0, n, nullptr, 0, sums,
+                                       workspace, static_cast<hipStream_t>(stream)));
+}
+
+int sketch_nystrom_rows(const float* B, int64_t n, int64_t r, int64_t ldb, const double* Cp,
+                        int64_t ldcp, int64_t row0, int64_t mr, double* out, int64_t ldo,
+                        void* workspace, size_t workspace_bytes, void* stream) {
+    int st = check_nystrom(B, n, r, ldb, Cp, ldcp, workspace, workspace_bytes);
+    if (st != SK_OK) return st;
+    if (row0 < 0 || mr < 0 || row0 > n - mr) return SK_EINVAL;
+    if (n == 0 || mr == 0) return SK_OK;
+    if (out == nullptr || ldo < n) return SK_EINVAL;
+    if ((uintptr_t)out & 7u) return SK_EALIGN;
+    return from_hip(sk::launch_nystrom(nullptr, 0, B, n, r, ldb, Cp, ldcp, row0, mr, out, ldo,
+                                       nullptr, workspace, static_cast<hipStream_t>(stream)));
+}
+
 }  // extern "C"

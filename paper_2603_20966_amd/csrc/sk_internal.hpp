@@ -202,6 +202,17 @@ hipError_t launch_gen_omega(uint64_t seed, int dist, int64_t row0, int64_t n, in
 hipError_t launch_quantize(const float* A, int64_t m, int64_t n, int64_t lda, int dst, void* Aq,
                            int64_t ldq, float* scales, hipStream_t s);
 
+// Nystrom core and reconstruction (FP64, sk_nystrom.hip).
+constexpr int64_t kPinvMaxR = 1024;
+size_t pinv_workspace_bytes(int64_t r);
+hipError_t launch_core_pinv(const void* C, int c_f64, int64_t r, int64_t ldc, double tol,
+                            int max_sweeps, double* Cp, int64_t ldcp, double* eig, int32_t* info,
+                            void* ws, hipStream_t s);
+size_t nystrom_workspace_bytes(int64_t n, int64_t r);
+hipError_t launch_nystrom(const float* A, int64_t lda, const float* B, int64_t n, int64_t r,
+                          int64_t ldb, const double* Cp, int64_t ldcp, int64_t row0, int64_t mr,
+                          double* out, int64_t ldo, double* sums, void* ws, hipStream_t s);
+
 // The C ABI's sketch_gen_matmul path, shared by the entry points that bring
 // their own workspace and by the one that uses the library's static scratch.
 // gen_matmul_validate makes no HIP call; *need receives the workspace bytes.

@@ -48,7 +48,7 @@ def test_header_symbols_exported():
 
 
 def test_version_and_status_strings():
-    assert sk.sketch_abi_version() == 5
+    assert sk.sketch_abi_version() == 6
     for st in range(-11, 1):
         assert sk.sketch_status_string(st) != "unknown status"
     assert sk.sketch_status_string(-100) == "unknown status"
@@ -307,3 +307,49 @@ def test_server_entry_points_reject_without_a_server():
                 (1 << 20, 4, 4, 9)):
         assert L.sk_server_create(*bad, ctypes.byref(h)) == EINVAL and not h.value
     assert L.sk_server_create(1 << 20, 4, 4, 2, None) == EINVAL
+
+
+def test_nystrom_entry_points_reject_on_host():
+    """Argument checks of the Nystrom core pseudo-inverse and reconstruction (Sec. 5, Alg. 2),
+    all found before anything is enqueued (no GPU needed)."""
+    L = sk.lib()
+    need = L.sketch_core_pinv_workspace(256)
+    assert need > 2 * 256 * 256 * 8 and L.sketch_core_pinv_workspace(1025) == 0
+    assert L.sketch_core_pinv_workspace(0) == 0
+
+    def pinv(C=PA, cdt=YF32, r=256, ldc=256, tol=1e-12, sw=16, Cp=PB, ldcp=256, eig=None,
+             info=None, ws=PW, wsb=1 << 30):
+        return L.sketch_core_pinv(C, cdt, r, ldc, tol, sw, Cp, ldcp, eig, info, ws, wsb, None)
+
+    assert pinv(cdt=2) == EDTYPE
+    assert pinv(r=1025) == EINVAL and pinv(r=-1) == EINVAL
+    assert pinv(tol=-1.0) == EINVAL and pinv(tol=float("nan")) == EINVAL and pinv(tol=2.0) == EINVAL
+    assert pinv(sw=0) == EINVAL and pinv(sw=101) == EINVAL
+    assert pinv(C=None) == EINVAL and pinv(Cp=None) == EINVAL
+    assert pinv(ldc=255) == EINVAL and pinv(ldcp=255) == EINVAL
+    assert pinv(C=PA + 2) == EALIGN and pinv(cdt=YF64, C=PA + 4) == EALIGN
+    assert pinv(Cp=PB + 4) == EALIGN and pinv(eig=PB + 4) == EALIGN and pinv(info=PB + 2) == EALIGN
+    assert pinv(ws=None) == EWS and pinv(wsb=need - 1) == EWS
+    assert pinv(r=0, C=None, Cp=None, ws=None) == OK
+    nneed = L.sketch_nystrom_workspace(2000, 64)
+    assert nneed >= 2000 * 64 * 8
+
+    def err(A=PA, n=2000, lda=2000, B=PB, r=64, ldb=64, Cp=PW, ldcp=64, sums=PB, ws=PW,
+            wsb=1 << 30):
+        return L.sketch_nystrom_error(A, n, lda, B, r, ldb, Cp, ldcp, sums, ws, wsb, None)
+
+    assert err(r=0) == EINVAL and err(r=1025) == EINVAL and err(n=-1) == EINVAL
+    assert err(A=None) == EINVAL and err(sums=None) == EINVAL and err(B=None) == EINVAL
+    assert err(lda=1999) == EINVAL and err(ldb=63) == EINVAL and err(ldcp=63) == EINVAL
+    assert err(A=PA + 2) == EALIGN and err(sums=PB + 4) == EALIGN and err(Cp=PW + 4) == EALIGN
+    assert err(ws=None) == EWS and err(wsb=nneed - 1) == EWS
+    assert err(n=64 * 65536, lda=64 * 65536) == EUNSUP
+    assert err(n=0, A=None, B=None, sums=None, ws=None) == OK
+
+    def rows(B=PB, n=2000, r=64, ldb=64, Cp=PW, ldcp=64, row0=0, mr=10, out=PA, ldo=2000, ws=PW,
+             wsb=1 << 30):
+        return L.sketch_nystrom_rows(B, n, r, ldb, Cp, ldcp, row0, mr, out, ldo, ws, wsb, None)
+
+    assert rows(row0=-1) == EINVAL and rows(row0=1995) == EINVAL and rows(mr=-1) == EINVAL
+    assert rows(out=None) == EINVAL and rows(ldo=1999) == EINVAL and rows(out=PA + 4) == EALIGN
+    assert rows(mr=0, out=None) == OK

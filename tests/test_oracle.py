@@ -500,3 +500,40 @@ def test_nystrom_oracle_closed_forms():
         errs.append(e)
     assert all(b <= a + 1e-12 for a, b in zip(errs, errs[1:])), errs
     assert errs[-1] < 0.5 * errs[0]
+
+
+def test_core_pinv_oracle_known_spectrum():
+    """The oracle's core pseudo-inverse (Sec. 5; eigenvalue cut of Sec. 6.2) on matrices
+    built from a known spectrum: C = U diag(lambda) U^T gives U diag(mu) U^T with
+    mu = 1/lambda above tol * max|lambda| and 0 below; the Moore-Penrose identities
+    hold for the kept part; a planted eigenvalue just below the cut is dropped and one
+    just above is kept; the symmetric part of a non-symmetric input is what is inverted."""
+    from oracle.nystrom import core_pinv
+
+    rng = np.random.default_rng(12)
+    r = 40
+    U, _ = np.linalg.qr(rng.standard_normal((r, r)))
+    lam = np.logspace(0, -6, r)
+    lam[5] = -0.25                 # indefinite: kept, inverted with its sign
+    lam[-3:] = [0.0, 0.5e-12, 2e-12]
+    C = (U * lam) @ U.T
+    mu = np.where(np.abs(lam) > 1e-12, 1.0 / np.where(lam == 0, 1, lam), 0.0)
+    want = (U * mu) @ U.T
+    got = core_pinv(C, 1e-12)
+    kappa = 1.0 / 2e-12
+    assert np.linalg.norm(got - want) <= 64 * r * 2.0 ** -53 * kappa * np.linalg.norm(want)
+    # dropping the two small planted eigenvalues: a clean projector identity on the rest
+    got6 = core_pinv(C, 1e-9)
+    P = got6 @ C
+    keep = np.abs(lam) > 1e-9
+    Pk = (U[:, keep]) @ U[:, keep].T
+    assert np.abs(P - Pk).max() <= 1e-8
+    kappa_kept = 1.0 / np.abs(lam[keep]).min()
+    assert np.abs(C @ got6 @ C - (U[:, keep] * lam[keep]) @ U[:, keep].T).max() <= \
+        64 * r * 2.0 ** -53 * kappa_kept
+    # only the symmetric part counts: M and M^T give the same result, and an antisymmetric
+    # addition leaves the (well-conditioned) kept part unchanged up to rounding
+    Sk = rng.standard_normal((r, r))
+    M = C + 1e-3 * (Sk - Sk.T)
+    assert np.array_equal(core_pinv(M, 1e-12), core_pinv(M.T, 1e-12))
+    assert np.linalg.norm(core_pinv(M, 1e-9) - got6) <= 1e-6 * np.linalg.norm(got6)
