@@ -80,89 +80,163 @@ __global__ __launch_bounds__(256) void k_jac_init(const TC* __restrict__ C, int6
     V[e] = (i == j) ? 1.0 : 0.0;
 }
 
-// Rotation annihilating a_pq of the symmetric 2x2 [[app, apq], [apq, aqq]]:
-// J = [[c, s], [-s, c]] with t = tan theta the smaller root of
-// t^2 + 2 tau t - 1 = 0, tau = (aqq - app) / (2 apq).  Identity when apq is zero
-// or negligible against sqrt(|app aqq|).
-__device__ __forceinline__ void jacobi_rotation(double app, double aqq, double apq, double& c,
-                                                double& s) {
-    c = 1.0;
-    s = 0.0;
-    if (apq == 0.0 || fabs(apq) <= 0x1p-60 * sqrt(fabs(app)) * sqrt(fabs(aqq))) return;
-    const double tau = (aqq - app) / (2.0 * apq);
-    double t;
-    if (fabs(tau) > 1e150) {
-        t = 0.5 / tau;
-    } else {
-        t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+// 1/sqrt(x) and 1/x for normal positive x: the hardware estimates refined by
+// two Newton steps (each squares the relative error).
+__device__ __forceinline__ double rsqrt_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    for (int i = 0; i < 2; ++i) {
+        const double e = fma(-(x * y), y, 1.0);
+        y = fma(0.5 * y, e, y);
     }
-    c = 1.0 / sqrt(1.0 + t * t);
-    s = t * c;
+    return y;
 }
 
-// One cyclic sweep of parallel 2x2 rotations on each pair's 32 x 32 diagonal
-// tile; Q_P (32 x 32, row-major) = the product of the sweep's rotations.
-__global__ __launch_bounds__(kJThreads) void k_jac_solve(const double* __restrict__ S, int64_t Rp,
-                                                         double* __restrict__ Q, int nb, int step,
-                                                         const JacState* st) {
+// Rotation for the symmetric 2x2 [[app, apq], [apq, aqq]]: J = [[c, s], [-s, c]]
+// with t = tan theta = sign(d) e / (|d| + sqrt(d^2 + e^2)), d = aqq - app,
+// e = 2 apq, the smaller root of the equation that zeroes the off-diagonal
+// entry.  t is evaluated in FP32 (d and e brought into [2^-64, 2^64] by a
+// power of two when they lie outside; an angle within a few 2^-24 of the
+// exact one leaves that fraction of apq), then c = (1 + t^2)^-1/2 and s = t c
+// in FP64, so that J is orthogonal to FP64 rounding.  Identity when apq = 0.
+__device__ __forceinline__ void jacobi_rotation(double app, double aqq, double apq, double& c,
+                                                double& s) {
+    double d = aqq - app, e = 2.0 * apq;
+    const double m = fmax(fabs(d), fabs(e));
+    if (m > 0x1p64 || m < 0x1p-64) {
+        int ex;
+        (void)frexp(m, &ex);
+        d = ldexp(d, -ex);
+        e = ldexp(e, -ex);
+    }
+    const float df = (float)d, ef = (float)e;
+    const float hf = __builtin_amdgcn_sqrtf(fmaf(df, df, ef * ef));
+    const float tf = (df >= 0.f ? ef : -ef) * __builtin_amdgcn_rcpf(fabsf(df) + hf);
+    const double t = (double)tf;
+    const double cc = rsqrt_nr(fma(t, t, 1.0));
+    c = apq == 0.0 ? 1.0 : cc;
+    s = apq == 0.0 ? 0.0 : t * cc;
+}
+
+// Pairing of the blocks in a launch: kFull pairs blocks (2i, 2i + 1) and runs
+// a full inner sweep (every pair of the tile's 32 indices); kCross pairs the
+// blocks by the circle method at the given step and rotates only the 256
+// pairs (one index of each block).  A sweep of the whole matrix is one kFull
+// launch and nb - 1 kCross launches: every pair of indices is rotated at least
+// once, in 31 + 16 (nb - 1) rounds.
+enum { kFull = 0, kCross = 1 };
+
+template <int MODE>
+__device__ __forceinline__ void pair_blocks(int nb, int step, int i, int& I, int& J) {
+    if (MODE == kFull) {
+        I = 2 * i;
+        J = 2 * i + 1;
+    } else {
+        circle_pair(nb, step, i, I, J);
+    }
+}
+
+// Inner schedule on the 32 positions of a pair tile: the pairs of a round are
+// always the positions (2i, 2i + 1); after each round the entry at position p
+// moves to sigma(p).
+//  kFull (31 rounds): position p starts with tile index p; sigma is the circle
+//   method seen from the positions: position 0 stays, the others carry an
+//   offset c in [0, 31) (position 1: c = 0, 2i: c = i, 2i + 1: c = 31 - i) that
+//   drops by one each round, so every pair of indices meets once.
+//  kCross (16 rounds): position 2k starts with index k of the first block and
+//   2k + 1 with index k of the second; even positions stay and the second
+//   block's indices step down one odd position per round, so each first-block
+//   index meets every second-block index once.
+// Both schedules return every index to its starting position.
+template <int MODE>
+__device__ __forceinline__ int tile_index(int p) {
+    return MODE == kFull ? p : (p & 1) ? kJB + p / 2 : p / 2;
+}
+__device__ __forceinline__ int pos_offset(int p) { return p == 1 ? 0 : (p & 1) ? kJT - 1 - p / 2 : p / 2; }
+__device__ __forceinline__ int offset_pos(int c) {
+    return c == 0 ? 1 : c < kJT / 2 ? 2 * c : 2 * (kJT - 1 - c) + 1;
+}
+template <int MODE>
+__device__ __forceinline__ int sigma(int p) {
+    if (MODE == kCross) return (p & 1) ? 2 * ((p / 2 + kJB - 1) % kJB) + 1 : p;
+    return p == 0 ? 0 : offset_pos((pos_offset(p) + kJT - 2) % (kJT - 1));
+}
+template <int MODE>
+constexpr int rounds() { return MODE == kFull ? kJT - 1 : kJB; }
+
+// One inner sweep on each pair's 32 x 32 diagonal tile; Q_P (32 x 32,
+// row-major) = the product of its rotations.  512 threads: thread (X, Y) of the
+// first 256 keeps the 2x2 block of rows 2X, 2X+1 and columns 2Y, 2Y+1 of the
+// tile in registers, the same thread of the second 256 that block of Q.  A
+// round computes the 16 rotations (on the diagonal blocks), applies them to
+// every block, and moves the entries to their next positions through LDS.
+constexpr int kSolveThreads = 2 * kJThreads;
+
+template <int MODE>
+__global__ __launch_bounds__(kSolveThreads) void k_jac_solve(const double* __restrict__ S,
+                                                             int64_t Rp, double* __restrict__ Q,
+                                                             int nb, int step, const JacState* st) {
     if (st->converged) return;
-    __shared__ double a[2][kJT][kJP];
-    __shared__ double q[2][kJT][kJP];
-    __shared__ double self_c[kJT], other_c[kJT];
-    __shared__ int partner[kJT];
-    const int tid = threadIdx.x;
+    __shared__ double al[kJT][kJP];
+    __shared__ double ql[kJT][kJP];
+    __shared__ double rc[kJT / 2], rs[kJT / 2];
+    const bool qrole = threadIdx.x >= kJThreads;
+    const int tid = threadIdx.x & (kJThreads - 1), X = tid / 16, Y = tid % 16;
     int I, J;
-    circle_pair(nb, step, blockIdx.x, I, J);
-    for (int u = 0; u < kPerThread; ++u) {
-        const int e = tid + kJThreads * u, x = e / kJT, y = e % kJT;
-        a[0][x][y] = S[tile_row(I, J, x) * Rp + tile_row(I, J, y)];
-        q[0][x][y] = (x == y) ? 1.0 : 0.0;
+    pair_blocks<MODE>(nb, step, blockIdx.x, I, J);
+    double a[2][2];
+    for (int u = 0; u < 2; ++u)
+        for (int v = 0; v < 2; ++v)
+            a[u][v] = qrole ? ((2 * X + u == 2 * Y + v) ? 1.0 : 0.0)
+                            : S[tile_row(I, J, tile_index<MODE>(2 * X + u)) * Rp +
+                                tile_row(I, J, tile_index<MODE>(2 * Y + v))];
+    int sx[2], sy[2];
+    for (int u = 0; u < 2; ++u) {
+        sx[u] = qrole ? 2 * X + u : sigma<MODE>(2 * X + u);    // Q's rows do not move
+        sy[u] = sigma<MODE>(2 * Y + u);
     }
-    __syncthreads();
-    int cur = 0;
-    for (int t = 0; t < kJT - 1; ++t) {
-        if (tid < kJT / 2) {
-            int p, r;
-            circle_pair(kJT, t, tid, p, r);
-            if (p > r) {
-                const int w = p;
-                p = r;
-                r = w;
-            }
-            double c, s;
-            jacobi_rotation(a[cur][p][p], a[cur][r][r], a[cur][p][r], c, s);
-            // column p of J is (c, -s) on rows (p, r); column r is (s, c)
-            self_c[p] = c;
-            other_c[p] = -s;
-            partner[p] = r;
-            self_c[r] = c;
-            other_c[r] = s;
-            partner[r] = p;
+    double (*buf)[kJP] = qrole ? ql : al;
+    for (int t = 0; t < rounds<MODE>(); ++t) {
+        if (!qrole && X == Y) {
+            double c, sn;
+            jacobi_rotation(a[0][0], a[1][1], a[0][1], c, sn);
+            rc[X] = c;
+            rs[X] = sn;
         }
         __syncthreads();
-        const int nxt = cur ^ 1;
-        for (int u = 0; u < kPerThread; ++u) {
-            const int e = tid + kJThreads * u, x = e / kJT, y = e % kJT;
-            const int xb = partner[x], yb = partner[y];
-            const double sx = self_c[x], ox = other_c[x], sy = self_c[y], oy = other_c[y];
-            // (J^T A J)(x, y) as (P1 + P4) + (P2 + P3): the same terms for (y, x), so the
-            // tile stays exactly symmetric
-            const double p1 = (sx * sy) * a[cur][x][y];
-            const double p4 = (ox * oy) * a[cur][xb][yb];
-            const double p2 = (sx * oy) * a[cur][x][yb];
-            const double p3 = (ox * sy) * a[cur][xb][y];
-            double v = (p1 + p4) + (p2 + p3);
-            if (y == xb && ox != 0.0) v = 0.0;     // the entry the rotation annihilates
-            a[nxt][x][y] = v;
-            q[nxt][x][y] = sy * q[cur][x][y] + oy * q[cur][x][yb];
+        // J of a pair: [[c, s], [-s, c]] on its two positions
+        const double cy = rc[Y], syn = rs[Y];
+        const double jy[2][2] = {{cy, syn}, {-syn, cy}};
+        double na[2][2];
+        if (qrole) {
+            for (int u = 0; u < 2; ++u)
+                for (int v = 0; v < 2; ++v) na[u][v] = a[u][v] * jy[v][v] + a[u][v ^ 1] * jy[v ^ 1][v];
+        } else {
+            const double cx = rc[X], sxn = rs[X];
+            const double jx[2][2] = {{cx, sxn}, {-sxn, cx}};
+            for (int u = 0; u < 2; ++u)
+                for (int v = 0; v < 2; ++v) {
+                    // (J_X^T A J_Y)(u, v) as (T(u,v) + T(u',v')) + (T(u,v') + T(u',v)),
+                    // T(i, j) = (J_X(i, u) J_Y(j, v)) A(i, j): block (Y, X) sums the same
+                    // terms, so the tile stays exactly symmetric
+                    const int ub = u ^ 1, vb = v ^ 1;
+                    const double t1 = (jx[u][u] * jy[v][v]) * a[u][v];
+                    const double t4 = (jx[ub][u] * jy[vb][v]) * a[ub][vb];
+                    const double t2 = (jx[u][u] * jy[vb][v]) * a[u][vb];
+                    const double t3 = (jx[ub][u] * jy[v][v]) * a[ub][v];
+                    na[u][v] = (t1 + t4) + (t2 + t3);
+                }
         }
+        for (int u = 0; u < 2; ++u)
+            for (int v = 0; v < 2; ++v) buf[sx[u]][sy[v]] = na[u][v];
         __syncthreads();
-        cur = nxt;
+        for (int u = 0; u < 2; ++u)
+            for (int v = 0; v < 2; ++v) a[u][v] = buf[2 * X + u][2 * Y + v];
     }
-    double* Qp = Q + (int64_t)blockIdx.x * kJT * kJT;
-    for (int u = 0; u < kPerThread; ++u) {
-        const int e = tid + kJThreads * u;
-        Qp[e] = q[cur][e / kJT][e % kJT];
+    if (qrole) {        // back at the starting positions: Q in tile-index order
+        double* Qp = Q + (int64_t)blockIdx.x * kJT * kJT;
+        for (int u = 0; u < 2; ++u)
+            for (int v = 0; v < 2; ++v)
+                Qp[tile_index<MODE>(2 * X + u) * kJT + tile_index<MODE>(2 * Y + v)] = a[u][v];
     }
 }
 
@@ -186,6 +260,7 @@ __device__ __forceinline__ void block_sum2(double& x, double& y, double (*red)[k
 // S <- Q^T S Q over the upper pair-tiles (blocks [0, nT)) and V <- V Q over
 // 32-row blocks of V (blocks [nT, nT + nV)).  Each S tile also writes its
 // squared off-diagonal and total norms (mirror counted) to part[2 b], part[2 b + 1].
+template <int MODE>
 __global__ __launch_bounds__(kJThreads) void k_jac_apply(double* __restrict__ S,
                                                          double* __restrict__ V, int64_t Rp,
                                                          const double* __restrict__ Q, int nb,
@@ -209,8 +284,8 @@ __global__ __launch_bounds__(kJThreads) void k_jac_apply(double* __restrict__ S,
         }
         const int pb = pa + b;
         int Ia, Ja, Ib, Jb;
-        circle_pair(nb, step, pa, Ia, Ja);
-        circle_pair(nb, step, pb, Ib, Jb);
+        pair_blocks<MODE>(nb, step, pa, Ia, Ja);
+        pair_blocks<MODE>(nb, step, pb, Ib, Jb);
         for (int v = 0; v < kPerThread; ++v) {
             const int e = tid + kJThreads * v, i = e / kJT, j = e % kJT;
             x[i][j] = S[tile_row(Ia, Ja, i) * Rp + tile_row(Ib, Jb, j)];
@@ -218,25 +293,29 @@ __global__ __launch_bounds__(kJThreads) void k_jac_apply(double* __restrict__ S,
             qb[i][j] = Q[(int64_t)pb * kJT * kJT + e];
         }
         __syncthreads();
-        for (int v = 0; v < kPerThread; ++v) {            // U = X Q_b
-            const int e = tid + kJThreads * v, i = e / kJT, j = e % kJT;
-            double acc = 0.0;
-            for (int z = 0; z < kJT; ++z) acc = fma(x[i][z], qb[z][j], acc);
-            u[i][j] = acc;
+        const int ti = tid / 16, tj = tid % 16;           // rows ti, ti+16; columns tj, tj+16
+        double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+        for (int z = 0; z < kJT; ++z) {                  // U = X Q_b
+            const double x0 = x[ti][z], x1 = x[ti + 16][z], q0 = qb[z][tj], q1 = qb[z][tj + 16];
+            acc[0][0] = fma(x0, q0, acc[0][0]);
+            acc[0][1] = fma(x0, q1, acc[0][1]);
+            acc[1][0] = fma(x1, q0, acc[1][0]);
+            acc[1][1] = fma(x1, q1, acc[1][1]);
+        }
+        for (int a2 = 0; a2 < 2; ++a2)
+            for (int b2 = 0; b2 < 2; ++b2) u[ti + 16 * a2][tj + 16 * b2] = acc[a2][b2];
+        __syncthreads();
+        double tacc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+        for (int z = 0; z < kJT; ++z) {                  // T = Q_a^T U
+            const double q0 = qa[z][ti], q1 = qa[z][ti + 16], u0 = u[z][tj], u1 = u[z][tj + 16];
+            tacc[0][0] = fma(q0, u0, tacc[0][0]);
+            tacc[0][1] = fma(q0, u1, tacc[0][1]);
+            tacc[1][0] = fma(q1, u0, tacc[1][0]);
+            tacc[1][1] = fma(q1, u1, tacc[1][1]);
         }
         __syncthreads();
-        double tv[kPerThread];
-        for (int v = 0; v < kPerThread; ++v) {            // T = Q_a^T U
-            const int e = tid + kJThreads * v, i = e / kJT, j = e % kJT;
-            double acc = 0.0;
-            for (int z = 0; z < kJT; ++z) acc = fma(qa[z][i], u[z][j], acc);
-            tv[v] = acc;
-        }
-        __syncthreads();
-        for (int v = 0; v < kPerThread; ++v) {
-            const int e = tid + kJThreads * v;
-            x[e / kJT][e % kJT] = tv[v];
-        }
+        for (int a2 = 0; a2 < 2; ++a2)
+            for (int b2 = 0; b2 < 2; ++b2) x[ti + 16 * a2][tj + 16 * b2] = tacc[a2][b2];
         __syncthreads();
         double off = 0.0, tot = 0.0;
         for (int v = 0; v < kPerThread; ++v) {
@@ -265,19 +344,25 @@ __global__ __launch_bounds__(kJThreads) void k_jac_apply(double* __restrict__ S,
     b -= nT;                                              // V role
     const int rb = b / np, pc = b % np;
     int Ic, Jc;
-    circle_pair(nb, step, pc, Ic, Jc);
+    pair_blocks<MODE>(nb, step, pc, Ic, Jc);
     for (int v = 0; v < kPerThread; ++v) {
         const int e = tid + kJThreads * v, i = e / kJT, j = e % kJT;
         x[i][j] = V[((int64_t)rb * kJT + i) * Rp + tile_row(Ic, Jc, j)];
         qa[i][j] = Q[(int64_t)pc * kJT * kJT + e];
     }
     __syncthreads();
-    for (int v = 0; v < kPerThread; ++v) {
-        const int e = tid + kJThreads * v, i = e / kJT, j = e % kJT;
-        double acc = 0.0;
-        for (int z = 0; z < kJT; ++z) acc = fma(x[i][z], qa[z][j], acc);
-        V[((int64_t)rb * kJT + i) * Rp + tile_row(Ic, Jc, j)] = acc;
+    const int ti = tid / 16, tj = tid % 16;
+    double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+    for (int z = 0; z < kJT; ++z) {
+        const double x0 = x[ti][z], x1 = x[ti + 16][z], q0 = qa[z][tj], q1 = qa[z][tj + 16];
+        acc[0][0] = fma(x0, q0, acc[0][0]);
+        acc[0][1] = fma(x0, q1, acc[0][1]);
+        acc[1][0] = fma(x1, q0, acc[1][0]);
+        acc[1][1] = fma(x1, q1, acc[1][1]);
     }
+    for (int a2 = 0; a2 < 2; ++a2)
+        for (int b2 = 0; b2 < 2; ++b2)
+            V[((int64_t)rb * kJT + ti + 16 * a2) * Rp + tile_row(Ic, Jc, tj + 16 * b2)] = acc[a2][b2];
 }
 
 // End of a sweep: sum the tiles' norms in tile order; converged when
@@ -299,41 +384,41 @@ __global__ __launch_bounds__(kJThreads) void k_jac_flag(const double* __restrict
 }
 
 // Fixed-shape FP64 tile engine: out(i, j) = sum_l X(i, l) Y(j, l) (times mu_l
-// when mu is given), l ascending, for a 64 x 64 tile per workgroup (256
-// threads, 4 x 4 outputs each, l in chunks of 16 staged in LDS).
+// when mu is given), l ascending, for a TM x TM tile per workgroup (256 threads,
+// (TM/16) x (TM/16) outputs each, l in chunks of 16 staged in LDS).
 constexpr int kGT = 64, kGK = 16;
 
-template <typename TX, typename TY>
+template <int TM, typename TX, typename TY>
 __device__ __forceinline__ void tile_accumulate(const TX* __restrict__ X, int64_t ldx, int64_t mx,
                                                 const TY* __restrict__ Y, int64_t ldy, int64_t my,
                                                 int64_t K, const double* mu, int64_t i0,
-                                                int64_t j0, double acc[4][4],
-                                                double (*xs)[kGT], double (*ys)[kGT]) {
+                                                int64_t j0, double acc[TM / 16][TM / 16],
+                                                double (*xs)[TM], double (*ys)[TM]) {
+    constexpr int R = TM / 16;                  // outputs per thread and dimension
     const int tid = threadIdx.x, ty = tid / 16, tx = tid % 16;
-    const int li = tid / 4, lk = (tid % 4) * 4;
-    for (int a = 0; a < 4; ++a)
-        for (int c = 0; c < 4; ++c) acc[a][c] = 0.0;
+    const int li = tid / (16 / R), lk = (tid % (16 / R)) * R;
+    for (int a = 0; a < R; ++a)
+        for (int c = 0; c < R; ++c) acc[a][c] = 0.0;
     for (int64_t l0 = 0; l0 < K; l0 += kGK) {
-        for (int w = 0; w < 4; ++w) {
+        for (int w = 0; w < R; ++w) {
             const int64_t l = l0 + lk + w;
             const int64_t gi = i0 + li, gj = j0 + li;
             xs[lk + w][li] = (gi < mx && l < K) ? (double)X[gi * ldx + l] : 0.0;
-            double yv = (gj < my && l < K) ? (double)Y[gj * ldy + l] : 0.0;
-            ys[lk + w][li] = yv;
+            ys[lk + w][li] = (gj < my && l < K) ? (double)Y[gj * ldy + l] : 0.0;
         }
         __syncthreads();
         const int kk_end = (int)((K - l0) < kGK ? (K - l0) : kGK);
         for (int kk = 0; kk < kk_end; ++kk) {
-            double xv[4], yv[4];
-            for (int a = 0; a < 4; ++a) xv[a] = xs[kk][ty * 4 + a];
-            for (int c = 0; c < 4; ++c) yv[c] = ys[kk][tx * 4 + c];
+            double xv[R], yv[R];
+            for (int a = 0; a < R; ++a) xv[a] = xs[kk][ty * R + a];
+            for (int c = 0; c < R; ++c) yv[c] = ys[kk][tx * R + c];
             if (mu) {
                 const double m = mu[l0 + kk];
-                for (int a = 0; a < 4; ++a)
-                    for (int c = 0; c < 4; ++c) acc[a][c] = fma(xv[a] * yv[c], m, acc[a][c]);
+                for (int a = 0; a < R; ++a)
+                    for (int c = 0; c < R; ++c) acc[a][c] = fma(xv[a] * yv[c], m, acc[a][c]);
             } else {
-                for (int a = 0; a < 4; ++a)
-                    for (int c = 0; c < 4; ++c) acc[a][c] = fma(xv[a], yv[c], acc[a][c]);
+                for (int a = 0; a < R; ++a)
+                    for (int c = 0; c < R; ++c) acc[a][c] = fma(xv[a], yv[c], acc[a][c]);
             }
         }
         __syncthreads();
@@ -348,7 +433,8 @@ __global__ __launch_bounds__(256) void k_pinv_form(const double* __restrict__ S,
                                                    const double* __restrict__ V, int64_t Rp,
                                                    int64_t r, double tol, double* __restrict__ Cp,
                                                    int64_t ldcp, double* __restrict__ eig) {
-    __shared__ double xs[kGK][kGT], ys[kGK][kGT];
+    constexpr int TM = 32;
+    __shared__ double xs[kGK][TM], ys[kGK][TM];
     __shared__ double mu[1024];
     __shared__ double red[256];
     const int tid = threadIdx.x;
@@ -367,13 +453,13 @@ __global__ __launch_bounds__(256) void k_pinv_form(const double* __restrict__ S,
         if (eig && blockIdx.x == 0 && blockIdx.y == 0) eig[l] = lam;
     }
     __syncthreads();
-    const int64_t i0 = (int64_t)blockIdx.y * kGT, j0 = (int64_t)blockIdx.x * kGT;
-    double acc[4][4];
-    tile_accumulate(V, Rp, r, V, Rp, r, r, mu, i0, j0, acc, xs, ys);
+    const int64_t i0 = (int64_t)blockIdx.y * TM, j0 = (int64_t)blockIdx.x * TM;
+    double acc[2][2];
+    tile_accumulate<TM>(V, Rp, r, V, Rp, r, r, mu, i0, j0, acc, xs, ys);
     const int ty = tid / 16, tx = tid % 16;
-    for (int a = 0; a < 4; ++a)
-        for (int c = 0; c < 4; ++c) {
-            const int64_t i = i0 + ty * 4 + a, j = j0 + tx * 4 + c;
+    for (int a = 0; a < 2; ++a)
+        for (int c = 0; c < 2; ++c) {
+            const int64_t i = i0 + ty * 2 + a, j = j0 + tx * 2 + c;
             if (i < r && j < r) Cp[i * ldcp + j] = acc[a][c];
         }
 }
@@ -386,7 +472,7 @@ __global__ __launch_bounds__(256) void k_bw(const float* __restrict__ B, int64_t
     __shared__ double xs[kGK][kGT], ys[kGK][kGT];
     const int64_t i0 = (int64_t)blockIdx.y * kGT, j0 = (int64_t)blockIdx.x * kGT;
     double acc[4][4];
-    tile_accumulate(B, ldb, mw, Cp, ldcp, r, r, (const double*)nullptr, i0, j0, acc, xs, ys);
+    tile_accumulate<kGT>(B, ldb, mw, Cp, ldcp, r, r, (const double*)nullptr, i0, j0, acc, xs, ys);
     const int ty = threadIdx.x / 16, tx = threadIdx.x % 16;
     for (int a = 0; a < 4; ++a)
         for (int c = 0; c < 4; ++c) {
@@ -408,7 +494,7 @@ __global__ __launch_bounds__(256) void k_nys_tile(const double* __restrict__ W, 
     __shared__ double red[2][kJThreads];
     const int64_t i0 = (int64_t)blockIdx.y * kGT, j0 = (int64_t)blockIdx.x * kGT;
     double acc[4][4];
-    tile_accumulate(W, r, mw, B, ldb, n, r, (const double*)nullptr, i0, j0, acc, xs, ys);
+    tile_accumulate<kGT>(W, r, mw, B, ldb, n, r, (const double*)nullptr, i0, j0, acc, xs, ys);
     const int ty = threadIdx.x / 16, tx = threadIdx.x % 16;
     double se = 0.0, sa = 0.0;
     for (int a = 0; a < 4; ++a)
@@ -493,15 +579,17 @@ hipError_t launch_core_pinv(const void* C, int c_f64, int64_t r, int64_t ldc, do
         k_jac_init<float><<<gi, 256, 0, s>>>(static_cast<const float*>(C), r, ldc, S, V, Rp, st);
     // off-diagonal Frobenius norm at most 8 Rp units of FP64 rounding of ||S||
     const double tolc = 8.0 * (double)Rp * 0x1p-53;
+    const unsigned ga = (unsigned)(nT + nV);
     for (int sw = 0; sw < max_sweeps; ++sw) {
-        for (int step = 0; step < nb - 1; ++step) {
-            k_jac_solve<<<(unsigned)np, kJThreads, 0, s>>>(S, Rp, Q, (int)nb, step, st);
-            k_jac_apply<<<(unsigned)(nT + nV), kJThreads, 0, s>>>(S, V, Rp, Q, (int)nb, step, part,
-                                                                   st);
+        k_jac_solve<kFull><<<(unsigned)np, kSolveThreads, 0, s>>>(S, Rp, Q, (int)nb, 0, st);
+        k_jac_apply<kFull><<<ga, kJThreads, 0, s>>>(S, V, Rp, Q, (int)nb, 0, part, st);
+        for (int step = 0; nb > 2 && step < nb - 1; ++step) {
+            k_jac_solve<kCross><<<(unsigned)np, kSolveThreads, 0, s>>>(S, Rp, Q, (int)nb, step, st);
+            k_jac_apply<kCross><<<ga, kJThreads, 0, s>>>(S, V, Rp, Q, (int)nb, step, part, st);
         }
         k_jac_flag<<<1, kJThreads, 0, s>>>(part, (int)nT, tolc, st);
     }
-    const unsigned gt = (unsigned)((r + kGT - 1) / kGT);
+    const unsigned gt = (unsigned)((r + 31) / 32);
     k_pinv_form<<<dim3(gt, gt), 256, 0, s>>>(S, V, Rp, r, tol, Cp, ldcp, eig);
     if (info) k_jac_info<<<1, 64, 0, s>>>(st, info);
     return hipGetLastError();
