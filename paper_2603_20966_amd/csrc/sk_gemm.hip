@@ -643,6 +643,13 @@ __global__ void k_reduce_partials(const float* __restrict__ partials, int S, int
 #pragma unroll
         for (int j = 0; j < 32; ++j) y += (double)v[j];
     }
+    for (; s + 8 <= S; s += 8) {
+        float v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = __builtin_nontemporal_load(p + (int64_t)(s + j) * sstride);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) y += (double)v[j];
+    }
     for (; s < S; ++s) y += (double)p[(int64_t)s * sstride];
     const int64_t off = y_trans ? c * ldy + r : r * ldy + c;
     if (y_f64) {
