@@ -194,8 +194,146 @@ __global__ __launch_bounds__(256) void k_gemm_cm(const CmArgs a) {
     }
 }
 
+// Few rows (m <= kSkinnyRows; e.g. B^T of the Nystrom second product with a
+// narrow sketch): the tile above would leave all but m/4 lanes of one wave
+// idle and walk each wave's 256 columns of a strip one load round at a time.
+// Here a workgroup takes one strip and one group of sketch columns; all its
+// threads stage the strip's columns of A (all 1024 at once for m <= 8 and
+// k <= 8, else 256 at a time) and their Omega rows in LDS, and thread (w, i, c) runs the chain that wave w of the tile kernel
+// runs for row i and sketch column c: columns j = w, w + 4, ... of the strip
+// in order, FP32 fma, then the four chains added in wave order.  Every sum is
+// the tile kernel's, bit for bit.
+constexpr int kSkinnyRows = 16;
+
+// SUB strip columns staged per step, MP rows (LDS pitch of a column).
+template <int K, int SUB, int MP>
+__global__ __launch_bounds__(256) void k_gemm_cm_skinny(const CmArgs a) {
+    constexpr int C = cm_strip_width(K);
+    constexpr int KP = (K + 3) / 4 * 4;
+    constexpr int CQ = (K + 3) / 4;                    // sketch columns per thread
+    static_assert(MP <= kSkinnyRows && C % SUB == 0 && SUB % 4 == 0, "staging geometry");
+    __shared__ __attribute__((aligned(16))) float om[SUB * KP];
+    __shared__ float as[SUB * MP];                     // as[j * MP + i] = A(i, j)
+    __shared__ float hand[3][MP][4 * CQ];
+
+    const int strip = (int)(blockIdx.x % a.S);
+    const int cg = (int)(blockIdx.x / a.S);
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6;                         // chain: columns j = wave (mod 4)
+    const int i = (tid & 63) >> 2;                     // row
+    const int cq = tid & 3;                            // sketch columns cq, cq + 4, ...
+    const int64_t col_begin = (int64_t)strip * C;
+    const int w = (int)min<int64_t>(C, a.n - col_begin);
+    const int c_base = cg * kColGroup;
+    const int kg = (int)min<int64_t>(kColGroup, a.k - c_base);
+    const int m = (int)a.m;
+
+    float acc[CQ];
+#pragma unroll
+    for (int u = 0; u < CQ; ++u) acc[u] = 0.0f;
+
+    for (int js = 0; js < w; js += SUB) {
+        const int sw = min(SUB, w - js);
+        // Omega rows js .. js + sw - 1 of the strip (quads cut by the step edges are
+        // generated by both steps; each entry is written from one of them)
+        const int64_t g0 = a.row0 + col_begin + js;
+        const int64_t q_lo = g0 >> 2;
+        const int nq = (int)(((g0 + sw - 1) >> 2) - q_lo + 1);
+        for (int it = tid; it < nq * kg; it += 256) {
+            const int qi = it / kg;
+            const int c = it - qi * kg;
+            const float4 z = omega4_dist((uint64_t)(q_lo + qi), a.col0 + (uint32_t)(c_base + c),
+                                         a.key0, a.key1, a.dist);
+            const float zz[4] = {z.x, z.y, z.z, z.w};
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t j = 4 * (q_lo + qi) + u - g0;
+                if (j >= 0 && j < sw) om[j * KP + c] = zz[u];
+            }
+        }
+        for (int e = tid; e < sw * m; e += 256) {
+            const int j = e / m, r = e - j * m;
+            as[j * MP + r] = a.A[(col_begin + js + j) * a.lda + r];
+        }
+        lds_barrier_c();
+        if (i < m) {
+            // the chain over columns j = wave (mod 4) of this step, in order (js is a
+            // multiple of 4); 8 columns' LDS reads are issued ahead of their fmas
+            auto step = [&](int j) {
+                const float x = as[j * MP + i];
+#pragma unroll
+                for (int u = 0; u < CQ; ++u) {
+                    const int c = cq + 4 * u;
+                    if (c < kg) acc[u] = __builtin_fmaf(x, om[j * KP + c], acc[u]);
+                }
+            };
+            int j = wave;
+            for (; j + 28 < sw; j += 32) {
+                float x[8], o[8][CQ];
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    x[t] = as[(j + 4 * t) * MP + i];
+#pragma unroll
+                    for (int u = 0; u < CQ; ++u) o[t][u] = om[(j + 4 * t) * KP + min(cq + 4 * u, KP - 1)];
+                }
+#pragma unroll
+                for (int t = 0; t < 8; ++t)
+#pragma unroll
+                    for (int u = 0; u < CQ; ++u)
+                        if (cq + 4 * u < kg) acc[u] = __builtin_fmaf(x[t], o[t][u], acc[u]);
+            }
+            for (; j < sw; j += 4) step(j);
+        }
+        lds_barrier_c();
+    }
+
+    if (wave > 0 && i < m) {
+#pragma unroll
+        for (int u = 0; u < CQ; ++u) hand[wave - 1][i][cq + 4 * u] = acc[u];
+    }
+    lds_barrier_c();
+    if (wave != 0 || i >= m) return;
+    const int64_t row = i;
+#pragma unroll
+    for (int u = 0; u < CQ; ++u) {
+        const int c = cq + 4 * u;
+        if (c >= kg) continue;
+        float v = acc[u];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) v += hand[q][i][c];
+        const int64_t col = c_base + c;
+        if (a.S == 1) {
+            const int64_t off = a.y_trans ? col * a.ldy + row : row * a.ldy + col;
+            double y = (double)v;
+            if (a.y_f64) {
+                double* Yp = static_cast<double*>(a.Y) + off;
+                if (a.beta) y += *Yp;
+                *Yp = y;
+            } else {
+                float* Yp = static_cast<float*>(a.Y) + off;
+                if (a.beta) y += (double)*Yp;
+                *Yp = (float)y;
+            }
+        } else {
+            a.partials[((int64_t)strip * a.m + row) * a.k + col] = v;
+        }
+    }
+}
+
 template <int K>
 hipError_t launch_cm_k(const CmArgs& a, hipStream_t s) {
+    if (a.m <= kSkinnyRows) {
+        const dim3 grid((unsigned)(a.S * ((a.k + kColGroup - 1) / kColGroup)));
+        if constexpr (K <= 8) {
+            if (a.m <= 8) {
+                hipLaunchKernelGGL((k_gemm_cm_skinny<K, cm_strip_width(K), 8>), grid, dim3(256), 0,
+                                   s, a);
+                return hipGetLastError();
+            }
+        }
+        hipLaunchKernelGGL((k_gemm_cm_skinny<K, 256, kSkinnyRows>), grid, dim3(256), 0, s, a);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL((k_gemm_cm<K>), dim3((unsigned)(8 * a.tiles8)), dim3(256), 0, s, a);
     return hipGetLastError();
 }

@@ -624,6 +624,184 @@ __global__ __launch_bounds__(kThreads) void k_gemm_cm_mfma(const CmMArgs a) {
     }
 }
 
+// Few rows (m <= 64; e.g. B^T of the Nystrom second product): the kernel above
+// gives a tile's 64 rows to one wave, which runs all 4 x NT accumulator chains
+// while the other seven idle, and the Omega generation then waits on the
+// chains.  Here a workgroup takes one strip and one N-tile of 16 sketch
+// columns, and its waves split the work: waves 0..3 each run one chain (row
+// set q = wave: rows 4j + q of lane j) with the steps, operands and order of
+// the kernel above, so the results equal it (and the row-major kernel) bit for
+// bit; waves 4..7 generate the Omega chunks, kSkG chunks per barrier, into the
+// other half of a double-buffered LDS ring.
+constexpr int kSkG = 8;
+
+template <int kKC, bool ALIGNED>
+__global__ __launch_bounds__(kThreads) void k_gemm_cm_mfma_skinny(const CmMArgs a) {
+    constexpr int BN = 16;
+    constexpr int kNS = kKC / 4;
+    constexpr int kLV = kKC / 16;
+    constexpr int kGenThreads = kThreads / 2;
+    __shared__ float om[2 * kSkG][BN][kKC + 4];
+
+    const int64_t tt = blockIdx.x;
+    if (tt >= a.tiles) return;
+    const int strip = (int)(tt % a.S);
+    const int nb = (int)(tt / a.S);
+    const int64_t col_begin = (int64_t)strip * kMfmaStrip;
+    const int n_base = nb * BN;
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const bool gen_wave = wave >= 4;
+    const int q = wave & 3;
+    const int g = lane >> 4;
+    const int j = lane & 15;
+    const int w = (int)min<int64_t>(kMfmaStrip, a.n - col_begin);
+    const int nchunks = (w + kKC - 1) / kKC;
+    const int ngroups = (nchunks + kSkG - 1) / kSkG;
+    const int kb = (int)min<int64_t>(BN, a.k - n_base);
+    const int64_t rl = 4 * j;                               // first row of the lane
+    const bool full_rows = rl + 3 < a.m;
+
+    // columns past k of every slot are zero (generation writes columns < kb only)
+    for (int it = threadIdx.x; it < 2 * kSkG * BN * (kKC + 4); it += kThreads) {
+        const int n = (it / (kKC + 4)) % BN;
+        if (n >= kb) (&om[0][0][0])[it] = 0.0f;
+    }
+    // chunks of group gi -> slots (gi & 1) * kSkG .. ; same values and layout as the
+    // tile kernel's chunks (zeros past the strip's end)
+    const int64_t gb = a.row0 + col_begin;
+    const int nq = (int)(((gb + kKC - 1) >> 2) - (gb >> 2) + 1);   // quads per chunk
+    auto gen_group = [&](int gi) {
+        const int c0 = gi * kSkG;
+        const int cnt = min(kSkG, nchunks - c0);
+        const int per = nq * kb;
+        for (int it = threadIdx.x - kGenThreads; it < cnt * per; it += kGenThreads) {
+            const int ci = it / per;
+            const int r = it - ci * per;
+            const int qi = r / kb;
+            const int n = r - qi * kb;
+            const int c = c0 + ci;
+            const int64_t g0 = gb + (int64_t)c * kKC;
+            const int kvalid = min(kKC, w - c * kKC);
+            const int64_t qq = (g0 >> 2) + qi;
+            const float4 z = omega4_dist((uint64_t)qq, a.col0 + (uint32_t)(n_base + n), a.key0,
+                                         a.key1, a.dist);
+            const int kl0 = (int)(4 * qq - g0);
+            float* dst = om[(gi & 1) * kSkG + ci][n];
+            const float zz[4] = {z.x, z.y, z.z, z.w};
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int kl = kl0 + u;
+                if (kl >= 0 && kl < kKC) dst[kl] = (kl < kvalid) ? zz[u] : 0.0f;
+            }
+        }
+    };
+
+    // ALIGNED (m a multiple of 4): every lane issues the same loads from a valid
+    // address (a lane without rows reads row 0: its sums are never stored; a column
+    // past the strip reads the strip's last column and is zeroed when its chunk is
+    // used), so the compiler can wait for each ring buffer alone instead of for every
+    // load in flight
+    const bool has_rows = rl < a.m;
+    const float* acol = a.A + (col_begin + g * kNS) * a.lda + (ALIGNED && !has_rows ? 0 : rl);
+    auto load_a = [&](v4f* x, int c) {
+        if (c >= nchunks) return;
+        const int kl = c * kKC + g * kNS;
+#pragma unroll
+        for (int s = 0; s < kNS; ++s) {
+            if constexpr (ALIGNED) {
+                const int cl = min(kl + s, w - 1) - g * kNS;     // column offset from acol
+                x[s] = *reinterpret_cast<const v4f*>(acol + (int64_t)cl * a.lda);
+            } else {
+                const float* p = acol + (int64_t)(c * kKC + s) * a.lda;
+                if (full_rows && kl + s < w) {
+                    x[s] = *reinterpret_cast<const v4f*>(p);
+                } else {
+                    v4f v = {0.f, 0.f, 0.f, 0.f};
+                    if (kl + s < w)
+                        for (int e = 0; e < 4; ++e)
+                            if (rl + e < a.m) v[e] = p[e];
+                    x[s] = v;
+                }
+            }
+        }
+    };
+
+    // A chunks in a ring of kDepth register buffers (chain waves only)
+    constexpr int kDepth = 4;
+    static_assert(kSkG % kDepth == 0, "ring steps per group");
+    v4f ab[kDepth][kNS];
+    v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
+    if (!gen_wave) {
+#pragma unroll
+        for (int d = 0; d < kDepth - 1; ++d) load_a(ab[d], d);
+    } else {
+        gen_group(0);
+    }
+    lds_barrier_m();
+    for (int gi = 0; gi < ngroups; ++gi) {
+        if (gen_wave) {
+            if (gi + 1 < ngroups) gen_group(gi + 1);
+        } else {
+            for (int c0 = gi * kSkG; c0 < (gi + 1) * kSkG; c0 += kDepth) {
+#pragma unroll
+                for (int d = 0; d < kDepth; ++d) {
+                    const int c = c0 + d;
+                    if (c < nchunks) {
+                        const float* ob = &om[(gi & 1) * kSkG + (c - gi * kSkG)][j][4 * kLV * g];
+                        v4f wop[kLV];
+#pragma unroll
+                        for (int v = 0; v < kLV; ++v) wop[v] = *reinterpret_cast<const v4f*>(ob + 4 * v);
+                        if (ALIGNED && (c + 1) * kKC > w) {      // the strip's partial last chunk
+                            const int kl = c * kKC + g * kNS;
+#pragma unroll
+                            for (int s = 0; s < kNS; ++s)
+                                if (kl + s >= w) ab[d][s] = v4f{0.f, 0.f, 0.f, 0.f};
+                        }
+#pragma unroll
+                        for (int v = 0; v < kLV; ++v)
+#pragma unroll
+                            for (int s = 0; s < 4; ++s)
+                                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wop[v][s], ab[d][4 * v + s][q],
+                                                                           acc, 0, 0, 0);
+                        load_a(ab[(d + kDepth - 1) % kDepth], c + kDepth - 1);
+                    }
+                }
+            }
+        }
+        lds_barrier_m();
+    }
+    if (gen_wave) return;
+
+    // lane (g, j) holds Y^T rows (sketch columns) 4g .. 4g + 3 of column j of the tile:
+    // Y[rl + q][n_base + 4g + r] = acc[r]
+    const int64_t row = rl + q;
+    if (row >= a.m) return;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int cn = 4 * g + r;
+        if (cn >= kb) continue;
+        const int64_t col = n_base + cn;
+        const float v = acc[r];
+        if (a.S == 1) {
+            const int64_t off = a.y_trans ? col * a.ldy + row : row * a.ldy + col;
+            double y = (double)v;
+            if (a.y_f64) {
+                double* Yp = static_cast<double*>(a.Y) + off;
+                if (a.beta) y += *Yp;
+                *Yp = y;
+            } else {
+                float* Yp = static_cast<float*>(a.Y) + off;
+                if (a.beta) y += (double)*Yp;
+                *Yp = (float)y;
+            }
+        } else {
+            a.partials[((int64_t)strip * a.m + row) * a.k + col] = v;
+        }
+    }
+}
+
 template <int NT, int KC>
 hipError_t launch_cm_mfma_nt(const CmMArgs& a, hipStream_t s) {
     hipLaunchKernelGGL((k_gemm_cm_mfma<NT, KC>), dim3((unsigned)(8 * a.tiles8)), dim3(kThreads), 0,
@@ -1065,9 +1243,10 @@ hipError_t launch_gemm_mfma_batch(const BatchArgs& a, int nt, int grid, hipStrea
 // this k), only A is re-read per column block.
 hipError_t launch_gemm_cm_mfma(const CmLaunch& g) {
     const int64_t S = (g.n + kMfmaStrip - 1) / kMfmaStrip;
-    const int64_t nrb = (g.m + kBM - 1) / kBM;
-    int nt = mfma_ntiles(g.k);
-    while (nt > 1 && S * nrb * ((g.k + 16 * nt - 1) / (16 * nt)) < device_cus()) nt /= 2;
+    const bool skinny = g.m <= 64;
+    const int64_t nrb = skinny ? 1 : (g.m + kBM - 1) / kBM;
+    int nt = skinny ? 1 : mfma_ntiles(g.k);
+    while (!skinny && nt > 1 && S * nrb * ((g.k + 16 * nt - 1) / (16 * nt)) < device_cus()) nt /= 2;
     const int64_t BN = 16 * nt;
     CmMArgs a{};
     a.A = g.A;
@@ -1094,7 +1273,15 @@ hipError_t launch_gemm_cm_mfma(const CmLaunch& g) {
     constexpr int KC = chunk_cols(8);
     static_assert(chunk_cols(1) == KC && chunk_cols(2) == KC && chunk_cols(4) == KC,
                   "one chunk width for every N-tile count of the row-major kernel");
-    switch (nt) {
+    if (skinny) {
+        if (g.m % 4 == 0)
+            hipLaunchKernelGGL((k_gemm_cm_mfma_skinny<KC, true>), dim3((unsigned)a.tiles),
+                               dim3(kThreads), 0, g.stream, a);
+        else
+            hipLaunchKernelGGL((k_gemm_cm_mfma_skinny<KC, false>), dim3((unsigned)a.tiles),
+                               dim3(kThreads), 0, g.stream, a);
+        e = hipGetLastError();
+    } else switch (nt) {
     case 1: e = launch_cm_mfma_nt<1, KC>(a, g.stream); break;
     case 2: e = launch_cm_mfma_nt<2, KC>(a, g.stream); break;
     case 4: e = launch_cm_mfma_nt<4, KC>(a, g.stream); break;

@@ -140,3 +140,21 @@ def test_nystrom_chain_against_oracle_chain():
     Cref = oracle.gen_tmatmul(Bref, 8, 0, 0, k)
     assert oracle.rel_fro(C, Cref) <= 1e-5
     assert oracle.rel_fro(C, C.T) <= 1e-5          # Omega^T A Omega is symmetric
+
+
+@pytest.mark.parametrize("p,k", [(1, 5), (5, 5), (16, 16), (7, 9), (17, 20), (64, 64), (40, 256),
+                                 (64, 17)])
+def test_few_row_kernels_equal_tall_rows(p, k):
+    """Few rows (m <= 16 on the VALU path, m <= 64 on the matrix cores; the shape of B^T in
+    the second Nystrom product) run on kernels that spread a strip's chains over a whole
+    workgroup; each chain is the tile kernel's, so a few-row call equals the matching rows
+    of a tall call bit for bit."""
+    n, P, r0 = 9000, 300, 100
+    A = normal_matrix(P, n, seed=p + k)
+    Ad = cm_dev(A)
+    Yt = sk.sketch_gen_matmul_cm(Ad, 9, k, omega_row0=2)          # 300 rows: tile kernels
+    Ys = sk.sketch_gen_matmul_cm(Ad[:p], 9, k, omega_row0=2)
+    assert torch.equal(Ys, Yt[:p])
+    Ys2 = sk.sketch_gen_matmul_cm(Ad[r0:r0 + p], 9, k, omega_row0=2, y_trans=True)
+    assert torch.equal(Ys2.t(), Yt[r0:r0 + p])
+    check(Ys.double().cpu().numpy(), A[:p], 9, 2, 0, k)
