@@ -233,7 +233,13 @@ __device__ __forceinline__ void omega_group(const MTile& t, float (*om)[BN][kKC 
     }
 }
 
-template <int NT, bool GEN>
+// FULL: every chunk of the launch is whole (block widths multiples of the chunk
+// width).  Then every lane issues the same A loads every chunk, unconditionally
+// (a load past the strip's end re-reads its last chunk, never used), and the
+// compiler waits for the chunk being multiplied alone; with the per-lane tail
+// path present it waits for every load in flight, including the next chunk's,
+// which undoes the double buffering.
+template <int NT, bool GEN, bool FULL = false>
 __device__ __forceinline__ void mfma_tile(const MTile& t, float (*om)[16 * NT][lds_row(NT)]) {
     constexpr int BN = 16 * NT;
     constexpr int kKC = chunk_cols(NT);
@@ -259,6 +265,16 @@ __device__ __forceinline__ void mfma_tile(const MTile& t, float (*om)[16 * NT][l
         arow[tm] = t.A + r * lda4 + (t.col_begin + 4 * kLV * g) * 4;
     }
     auto load_a = [&](v4f (*a)[kLV], int c) {
+        if constexpr (FULL) {
+            const int cc = c < nchunks ? c : nchunks - 1;
+#pragma unroll
+            for (int tm = 0; tm < kTM; ++tm) {
+                const unsigned char* p = arow[tm] + (int64_t)cc * kKC * 4;
+#pragma unroll
+                for (int v = 0; v < kLV; ++v) a[tm][v] = *reinterpret_cast<const v4f*>(p + 16 * v);
+            }
+            return;
+        }
         if (c >= nchunks) return;
         const int kl = c * kKC + 4 * kLV * g;               // local column of component 0
 #pragma unroll
@@ -341,7 +357,7 @@ __device__ __forceinline__ void mfma_tile(const MTile& t, float (*om)[16 * NT][l
 }
 
 // One call: grid (strips of all blocks, 512-row tiles, sketch-column blocks).
-template <int NT, bool GEN>
+template <int NT, bool GEN, bool FULL>
 __global__ __launch_bounds__(kThreads) void k_gemm_mfma(const MArgs args) {
     __shared__ float om[2][16 * NT][lds_row(NT)];
     const int strip = blockIdx.x;
@@ -377,7 +393,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm_mfma(const MArgs args) {
     t.partials = args.partials;
     t.strip = strip;
     t.single = (args.S_total == 1);
-    mfma_tile<NT, GEN>(t, om);
+    mfma_tile<NT, GEN, FULL>(t, om);
 }
 
 // A batch of independent requests (serving): the tiles of each request are the
@@ -858,7 +874,8 @@ __device__ __forceinline__ void fp8x4_to_bf16(uint32_t w, uint32_t& lo2, uint32_
     }
 }
 
-template <int NT, int ADT, int W, bool GEN>
+// FULL: whole chunks only, unconditional A loads (as in mfma_tile).
+template <int NT, int ADT, int W, bool GEN, bool FULL = false>
 __device__ __forceinline__ void lp_tile(const MTile& t, uint16_t (*oh)[16 * NT][lp_row(ADT)],
                                         uint16_t (*ol)[16 * NT][lp_row(ADT)]) {
     constexpr int BN = 16 * NT;
@@ -892,6 +909,16 @@ __device__ __forceinline__ void lp_tile(const MTile& t, uint16_t (*oh)[16 * NT][
     // only when the chunk is consumed, so the loads stay in flight behind the
     // current chunk's MFMAs
     auto load_a = [&](v4u (*a)[RW], int c) {
+        if constexpr (FULL) {
+            const int cc = c < nchunks ? c : nchunks - 1;
+#pragma unroll
+            for (int tm = 0; tm < kTM; ++tm) {
+                const unsigned char* p = arow[tm] + (int64_t)cc * KC * es;
+#pragma unroll
+                for (int v = 0; v < RW; ++v) a[tm][v] = *reinterpret_cast<const v4u*>(p + 16 * v);
+            }
+            return;
+        }
         if (c >= nchunks) return;
         const int kl = c * KC + KG * g;
 #pragma unroll
@@ -1036,7 +1063,7 @@ __device__ __forceinline__ void lp_tile(const MTile& t, uint16_t (*oh)[16 * NT][
 // with three, a quarter of the tiles run as a tail on an underfilled chip).
 constexpr int lp_min_waves(int nt, int w) { return nt == 1 && w == 4 ? 4 : 1; }
 
-template <int NT, int ADT, int W, bool GEN>
+template <int NT, int ADT, int W, bool GEN, bool FULL>
 __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(lp_min_waves(NT, W))))
 void k_gemm_mfma_lp(const MArgs args) {
     __shared__ uint16_t oh[2][16 * NT][lp_row(ADT)];
@@ -1074,7 +1101,7 @@ void k_gemm_mfma_lp(const MArgs args) {
     t.partials = args.partials;
     t.strip = strip;
     t.single = (args.S_total == 1);
-    lp_tile<NT, ADT, W, GEN>(t, oh, ol);
+    lp_tile<NT, ADT, W, GEN, FULL>(t, oh, ol);
 }
 
 // Batch of requests of one class (serving); rows per tile = kLpBatchRows.
@@ -1127,7 +1154,14 @@ __global__ __launch_bounds__(64 * kLpBatchWaves) void k_gemm_mfma_lp_batch(const
 template <int NT, int ADT, int W, bool GEN>
 hipError_t launch_lp(const MArgs& a, dim3 grid, hipStream_t s) {
     grid.y = (unsigned)((a.m + 64 * W - 1) / (64 * W));
-    hipLaunchKernelGGL((k_gemm_mfma_lp<NT, ADT, W, GEN>), grid, dim3(64 * W), 0, s, a);
+    // whole chunks: unconditional loads (one N-tile measured 5% slower with them: its
+    // 4-wave, 128-register tiles already keep enough loads in flight)
+    bool full = NT > 1;
+    for (int b = 0; b < a.P; ++b) full = full && a.blk[b].n % lp_kc(ADT) == 0;
+    if (full)
+        hipLaunchKernelGGL((k_gemm_mfma_lp<NT, ADT, W, GEN, true>), grid, dim3(64 * W), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_gemm_mfma_lp<NT, ADT, W, GEN, false>), grid, dim3(64 * W), 0, s, a);
     return hipGetLastError();
 }
 
@@ -1147,7 +1181,12 @@ hipError_t dispatch_lp(int nt, int waves, const MArgs& a, dim3 grid, hipStream_t
 
 template <int NT, bool GEN>
 hipError_t launch_m(const MArgs& a, dim3 grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_gemm_mfma<NT, GEN>), grid, dim3(kThreads), 0, s, a);
+    bool full = true;
+    for (int b = 0; b < a.P; ++b) full = full && a.blk[b].n % chunk_cols(NT) == 0;
+    if (full)
+        hipLaunchKernelGGL((k_gemm_mfma<NT, GEN, true>), grid, dim3(kThreads), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_gemm_mfma<NT, GEN, false>), grid, dim3(kThreads), 0, s, a);
     return hipGetLastError();
 }
 
