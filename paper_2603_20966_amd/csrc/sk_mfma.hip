@@ -473,7 +473,11 @@ struct CmMArgs {
 
 // KC = the row-major kernel's chunk for this k (chunk_cols(mfma_ntiles(k))),
 // whatever N-tile count the launch picked, so that the sums are the same.
-template <int NT, int kKC>
+// FULL (m a multiple of 4, whole chunks): every lane of every wave issues the same
+// loads each chunk from a valid address (a lane or wave without rows reads row 0;
+// its sums are never stored; a load past the strip's end re-reads its last chunk),
+// so the compiler waits for the chunk in use alone (see mfma_tile).
+template <int NT, int kKC, bool FULL>
 __global__ __launch_bounds__(kThreads) void k_gemm_cm_mfma(const CmMArgs a) {
     constexpr int BN = 16 * NT;
     constexpr int kNS = kKC / 4;     // MFMA steps (and 16-byte loads per lane) per chunk
@@ -512,8 +516,15 @@ __global__ __launch_bounds__(kThreads) void k_gemm_cm_mfma(const CmMArgs a) {
     const bool full_rows = rl + 3 < a.m;
 
     // ---- A loads: step s of chunk c is column col_begin + c*KC + g*KC/4 + s --------
-    const float* acol = a.A + (t.col_begin + g * kNS) * a.lda + rl;
+    const float* acol = a.A + (t.col_begin + g * kNS) * a.lda + (FULL && rl >= a.m ? 0 : rl);
     auto load_a = [&](v4f* x, int c) {
+        if constexpr (FULL) {
+            const int cc = c < nchunks ? c : nchunks - 1;
+#pragma unroll
+            for (int s = 0; s < kNS; ++s)
+                x[s] = *reinterpret_cast<const v4f*>(acol + (int64_t)(cc * kKC + s) * a.lda);
+            return;
+        }
         if (!active || c >= nchunks) return;
         const int kl = c * kKC + g * kNS;
 #pragma unroll
@@ -820,8 +831,11 @@ __global__ __launch_bounds__(kThreads) void k_gemm_cm_mfma_skinny(const CmMArgs 
 
 template <int NT, int KC>
 hipError_t launch_cm_mfma_nt(const CmMArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL((k_gemm_cm_mfma<NT, KC>), dim3((unsigned)(8 * a.tiles8)), dim3(kThreads), 0,
-                       s, a);
+    const dim3 grid((unsigned)(8 * a.tiles8));
+    if (a.m % 4 == 0 && a.n % KC == 0)
+        hipLaunchKernelGGL((k_gemm_cm_mfma<NT, KC, true>), grid, dim3(kThreads), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_gemm_cm_mfma<NT, KC, false>), grid, dim3(kThreads), 0, s, a);
     return hipGetLastError();
 }
 
