@@ -1056,16 +1056,32 @@ __device__ __forceinline__ void lp_tile(const MTile& t, uint16_t (*oh)[16 * NT][
         }
     };
 
-    for (int c = 0; c < nchunks; c += 2) {
-        if (c + 1 < nchunks) make_chunk(c + 1);
-        compute(a0, c);
-        load_a(a0, c + 2);
-        lds_barrier_m();
-        if (c + 1 < nchunks) {
-            if (c + 2 < nchunks) make_chunk(c + 2);
-            compute(a1, c + 1);
-            load_a(a1, c + 3);
+    if constexpr (FULL) {
+        // the same order with every load issued (and kept ahead of the next chunk's work)
+        for (int c = 0; c < nchunks; c += 2) {
+            if (c + 1 < nchunks) make_chunk(c + 1);
+            compute(a0, c);
+            load_a(a0, c + 2);
+            __builtin_amdgcn_sched_barrier(0);
             lds_barrier_m();
+            if (c + 2 < nchunks) make_chunk(c + 2);
+            if (c + 1 < nchunks) compute(a1, c + 1);
+            load_a(a1, c + 3);
+            __builtin_amdgcn_sched_barrier(0);
+            lds_barrier_m();
+        }
+    } else {
+        for (int c = 0; c < nchunks; c += 2) {
+            if (c + 1 < nchunks) make_chunk(c + 1);
+            compute(a0, c);
+            load_a(a0, c + 2);
+            lds_barrier_m();
+            if (c + 1 < nchunks) {
+                if (c + 2 < nchunks) make_chunk(c + 2);
+                compute(a1, c + 1);
+                load_a(a1, c + 3);
+                lds_barrier_m();
+            }
         }
     }
     store_tile<NT>(t, acc, row_base, kb, g, i16);
@@ -1168,7 +1184,7 @@ __global__ __launch_bounds__(64 * kLpBatchWaves) void k_gemm_mfma_lp_batch(const
 template <int NT, int ADT, int W, bool GEN>
 hipError_t launch_lp(const MArgs& a, dim3 grid, hipStream_t s) {
     grid.y = (unsigned)((a.m + 64 * W - 1) / (64 * W));
-    // whole chunks: unconditional loads (one N-tile measured 5% slower with them: its
+    // whole chunks: unconditional loads (one N-tile measured 5-8% slower with them: its
     // 4-wave, 128-register tiles already keep enough loads in flight)
     bool full = NT > 1;
     for (int b = 0; b < a.P; ++b) full = full && a.blk[b].n % lp_kc(ADT) == 0;
