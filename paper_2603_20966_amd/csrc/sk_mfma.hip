@@ -733,7 +733,11 @@ __global__ __launch_bounds__(kThreads) void k_gemm_cm_mfma_skinny(const CmMArgs 
     const bool has_rows = rl < a.m;
     const float* acol = a.A + (col_begin + g * kNS) * a.lda + (ALIGNED && !has_rows ? 0 : rl);
     auto load_a = [&](v4f* x, int c) {
-        if (c >= nchunks) return;
+        if constexpr (ALIGNED) {
+            c = min(c, nchunks - 1);          // past the end: the last chunk again, never used
+        } else {
+            if (c >= nchunks) return;
+        }
         const int kl = c * kKC + g * kNS;
 #pragma unroll
         for (int s = 0; s < kNS; ++s) {
@@ -792,7 +796,12 @@ __global__ __launch_bounds__(kThreads) void k_gemm_cm_mfma_skinny(const CmMArgs 
                             for (int s = 0; s < 4; ++s)
                                 acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wop[v][s], ab[d][4 * v + s][q],
                                                                            acc, 0, 0, 0);
+                        if constexpr (!ALIGNED) load_a(ab[(d + kDepth - 1) % kDepth], c + kDepth - 1);
+                    }
+                    if constexpr (ALIGNED) {
+                        // every step issues its loads (the compiler then waits for one buffer)
                         load_a(ab[(d + kDepth - 1) % kDepth], c + kDepth - 1);
+                        __builtin_amdgcn_sched_barrier(0);
                     }
                 }
             }
