@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define SKETCH_ABI_VERSION 6
+#define SKETCH_ABI_VERSION 7
 
 enum sk_status {
     SK_OK = 0,
@@ -101,7 +101,12 @@ int64_t sketch_strip_width(int a_dtype, int64_t k);
 
 /* Bytes of device workspace a call needs (0 if none).  The workspace holds
  * the FP32 partial sums of the column strips between the streaming kernel and
- * the FP64 reduction kernel of one call; its contents need no preparation.
+ * the FP64 reduction kernel of one call (more than one strip), and, for BF16
+ * or FP8 A with k > 16, the call's Omega as two BF16 planes (the hi and lo
+ * terms of each entry, 2 * S * 4096 * kpad values, S strips, kpad = k rounded
+ * up to a multiple of 32 for k <= 32, of 64 beyond), formed by the call
+ * itself at a 256-byte aligned offset after the partials.  Its contents need
+ * no preparation.
  * One workspace serves one call at a time: calls that may run concurrently
  * (different streams) need separate workspaces.
  *   op = 0: sketch_gen_matmul / sketch_matmul_omega with an n-column A;

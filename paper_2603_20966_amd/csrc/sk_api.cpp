@@ -27,7 +27,7 @@ sk::TraceEvents take_trace() {
 size_t workspace_for(int op, int adtype, int64_t m, int64_t n, int64_t k, int64_t P) {
     const int64_t C = sk::strip_width_for(adtype, k);
     const int64_t S = (op == 0) ? (n + C - 1) / C : n / C + P;
-    return sk::gemm_workspace_bytes(m, S, k);
+    return sk::product_workspace_bytes(adtype, m, S, k);
 }
 
 int check_workspace(size_t need, const void* ws, size_t bytes) {
@@ -239,8 +239,8 @@ static int gen_matmul_reduce_impl(const void* const* A_b, int64_t P, int a_dtype
     g.stream = static_cast<hipStream_t>(stream);
     g.trace = trace;
     const int64_t S = sk::count_strips(g);
-    st = check_workspace(n_total > 0 ? sk::gemm_workspace_bytes(m, S, k) : 0, workspace,
-                         workspace_bytes);
+    st = check_workspace(n_total > 0 ? sk::product_workspace_bytes(a_dtype, m, S, k) : 0,
+                         workspace, workspace_bytes);
     if (st != SK_OK) return st;
     return run_product(g, n_total);
 }

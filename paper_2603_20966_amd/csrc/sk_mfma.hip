@@ -72,8 +72,57 @@ struct MArgs {
     int S_total;
     int y_f64;
     int beta;
+    const uint16_t* opack;    // low-precision path: packed Omega, hi plane
+    const uint16_t* opack_lo; // and lo plane
+    int64_t kpad;             // sketch columns per packed chunk (k rounded up to the N-tile)
+    int64_t nrt;              // row tiles
+    int nblk;                 // sketch-column blocks
     BlockDesc blk[kMaxBlocks];
 };
+
+// Tile of this workgroup in a one-dimensional grid of 8 * ceil(T / 8)
+// workgroups over T = nblk * S_total * nrt tiles.
+// XCD (low-precision kernel): workgroups are handed to the 8 XCDs
+// round-robin, so XCD x runs ids x, x + 8, ...; mapping them to the contiguous
+// tile range [x * T8, (x + 1) * T8), ordered sketch-column block fastest, then
+// strip, then row tile, makes each XCD read whole rows of A (every strip of a
+// row tile at once) and keeps the column blocks of one (strip, row tile) in
+// one L2.  Measured on 32768^2 FP8 at k = 64: 290 us against 371 with the
+// strip index fastest across XCDs.
+// Otherwise (FP32 kernel, measured 2-3% faster so at k = 64): the id is the
+// tile, strip fastest, then row tile, then column block.
+// Returns false for the padding ids past T.
+struct TileId {
+    int strip;
+    int64_t rtile;
+    int nb;
+};
+template <bool XCD>
+__device__ __forceinline__ bool mfma_tile_id(const MArgs& a, TileId& id) {
+    const int64_t T = (int64_t)a.nblk * a.S_total * a.nrt;
+    const int64_t v = blockIdx.x;
+    if constexpr (XCD) {
+        const int64_t T8 = (T + 7) / 8;
+        const int64_t t = (v % 8) * T8 + v / 8;
+        if (t >= T) return false;
+        id.nb = (int)(t % a.nblk);
+        const int64_t r = t / a.nblk;
+        id.strip = (int)(r % a.S_total);
+        id.rtile = r / a.S_total;
+    } else {
+        if (v >= T) return false;
+        id.strip = (int)(v % a.S_total);
+        const int64_t r = v / a.S_total;
+        id.rtile = r % a.nrt;
+        id.nb = (int)(r / a.nrt);
+    }
+    return true;
+}
+
+dim3 mfma_grid(const MArgs& a) {
+    const int64_t T = (int64_t)a.nblk * a.S_total * a.nrt;
+    return dim3((unsigned)(8 * ((T + 7) / 8)));
+}
 
 __device__ __forceinline__ void lds_barrier_m() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
@@ -101,6 +150,9 @@ struct MTile {
     float* partials;
     int64_t strip;            // strip index in the partial array
     bool single;
+    const uint16_t* opack;    // packed Omega of the call (low-precision path), hi plane
+    const uint16_t* opack_lo; // and lo plane
+    int64_t kpad;
 };
 
 // Write a wave's accumulators: lane (g, j) holds rows 4g..4g+3 and column j of
@@ -356,11 +408,14 @@ __device__ __forceinline__ void mfma_tile(const MTile& t, float (*om)[16 * NT][l
     store_tile<NT>(t, acc, row_base, kb, g, i16);
 }
 
-// One call: grid (strips of all blocks, 512-row tiles, sketch-column blocks).
+// One call: one workgroup per (strip of any block, 512-row tile, sketch-column
+// block), strip fastest.
 template <int NT, bool GEN, bool FULL>
 __global__ __launch_bounds__(kThreads) void k_gemm_mfma(const MArgs args) {
     __shared__ float om[2][16 * NT][lds_row(NT)];
-    const int strip = blockIdx.x;
+    TileId id;
+    if (!mfma_tile_id<false>(args, id)) return;
+    const int strip = id.strip;
     int b = 0;
     int64_t sib = strip;
     for (; b < args.P; ++b) {
@@ -378,8 +433,8 @@ __global__ __launch_bounds__(kThreads) void k_gemm_mfma(const MArgs args) {
     t.m = args.m;
     t.k = args.k;
     t.col_begin = sib * kMfmaStrip;
-    t.block_row = (int64_t)blockIdx.y * kBM;
-    t.n_base = blockIdx.z * 16 * NT;
+    t.block_row = id.rtile * kBM;
+    t.n_base = id.nb * 16 * NT;
     t.key0 = args.key0;
     t.key1 = args.key1;
     t.col0 = args.col0;
@@ -393,6 +448,9 @@ __global__ __launch_bounds__(kThreads) void k_gemm_mfma(const MArgs args) {
     t.partials = args.partials;
     t.strip = strip;
     t.single = (args.S_total == 1);
+    t.opack = nullptr;
+    t.opack_lo = nullptr;
+    t.kpad = 0;
     mfma_tile<NT, GEN, FULL>(t, om);
 }
 
@@ -438,6 +496,9 @@ __global__ __launch_bounds__(kThreads) void k_gemm_mfma_batch(const BatchArgs ar
         t.partials = rq.partials;
         t.strip = strip;
         t.single = (rq.strips == 1);
+        t.opack = nullptr;
+        t.opack_lo = nullptr;
+        t.kpad = 0;
         if (!first) lds_barrier_m();   // every wave is done with the previous tile's LDS
         first = false;
         mfma_tile<NT, true>(t, om);
@@ -897,8 +958,105 @@ __device__ __forceinline__ void fp8x4_to_bf16(uint32_t w, uint32_t& lo2, uint32_
     }
 }
 
+// ---- Omega of a whole call, split and laid out for the low-precision tiles ----
+// Every row tile of a strip multiplies the same Omega chunks, so a call's
+// Omega (hi, lo) is formed once, before the product, instead of once per
+// 64W-row tile (a 32768-row FP8 call has 64 tiles per strip).  Layout, one
+// plane for hi and one for lo: chunk gc = strip * (kLpStrip / KC) + c, then
+// sketch column n in [0, kpad), then contraction column kl in [0, KC):
+// element ((gc * kpad + n) * KC + kl).  A tile's BN columns of a chunk are
+// then one contiguous run of BN * KC values.  Entries past the strip's last
+// column and sketch columns >= k hold zero; the values are those the fused
+// generation writes into LDS, so both routes give the same sums bit for bit.
+struct PackArgs {
+    uint16_t* hi;
+    uint16_t* lo;
+    int64_t k, kpad;
+    uint32_t key0, key1, col0;
+    int dist;
+    const float* omega;       // stored Omega (n x k, ldo), or nullptr: generated
+    int64_t ldo;
+    int P;
+    BlockDesc blk[kMaxBlocks];
+};
+
+// sketch columns per packing workgroup: 16 gives each compute unit several
+// workgroups to interleave (the work is a chain of dependent arithmetic)
+constexpr int kPackRows = 16;
+
+// grid (chunks of all strips, ceil(kpad / 16)); 256 threads
+template <int ADT, bool GEN>
+__global__ __launch_bounds__(256) void k_lp_pack(const PackArgs a) {
+    constexpr int KC = lp_kc(ADT);
+    constexpr int R = lp_row(ADT);
+    constexpr int CPS = kLpStrip / KC;
+    __shared__ __attribute__((aligned(16))) uint16_t sh[2][kPackRows][R];
+    const int tid = threadIdx.x;
+    const int64_t gc = blockIdx.x;
+    const int64_t strip = gc / CPS;
+    const int c = (int)(gc - strip * CPS);
+    int b = 0;
+    int64_t sib = strip;
+    for (; b < a.P; ++b) {
+        const int64_t sb = (a.blk[b].n + kLpStrip - 1) / kLpStrip;
+        if (sib < sb) break;
+        sib -= sb;
+    }
+    const int64_t col_begin = sib * kLpStrip;
+    const int w = (int)min<int64_t>(kLpStrip, a.blk[b].n - col_begin);
+    if (c * KC >= w) return;                      // past the strip's end: never read
+    const int kvalid = min(KC, w - c * KC);
+    const int nb0 = blockIdx.y * kPackRows;
+    const int kb = (int)min<int64_t>(kPackRows, a.k - nb0);   // <= 0: all zero
+    static_assert((2 * kPackRows * R) % 8 == 0, "whole 16-byte pieces");
+    for (int it = tid; it < 2 * kPackRows * R / 8; it += 256)
+        reinterpret_cast<v4u*>(&sh[0][0][0])[it] = v4u{0u, 0u, 0u, 0u};
+    __syncthreads();
+    if constexpr (GEN) {
+        const int64_t g0 = a.blk[b].row0 + col_begin + (int64_t)c * KC;
+        const int64_t q_lo = g0 >> 2;
+        const int nq = (int)(((g0 + KC - 1) >> 2) - q_lo + 1);
+        const int items = kb > 0 ? nq * kb : 0;
+        for (int it = tid; it < items; it += 256) {
+            const int qi = it / kb;
+            const int n = it - qi * kb;
+            const float4 z = omega4_dist((uint64_t)(q_lo + qi), a.col0 + (uint32_t)(nb0 + n),
+                                         a.key0, a.key1, a.dist);
+            const int kl0 = (int)(4 * (q_lo + qi) - g0);
+            const float zz[4] = {z.x, z.y, z.z, z.w};
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int kl = kl0 + u;
+                if (kl >= 0 && kl < kvalid) split_bf16(zz[u], sh[0][n][kl], sh[1][n][kl]);
+            }
+        }
+    } else {
+        const int items = kb > 0 ? kvalid * kb : 0;
+        for (int it = tid; it < items; it += 256) {
+            const int kl = it / kb;
+            const int n = it - kl * kb;
+            split_bf16(a.omega[(col_begin + (int64_t)c * KC + kl) * a.ldo + nb0 + n],
+                       sh[0][n][kl], sh[1][n][kl]);
+        }
+    }
+    __syncthreads();
+    const int rows = (int)min<int64_t>(kPackRows, a.kpad - nb0);
+    const int pieces = rows * (KC / 8);           // 16-byte pieces per plane
+    for (int it = tid; it < 2 * pieces; it += 256) {
+        const int pl = it >= pieces;
+        const int q = it - pl * pieces;
+        const int n = q / (KC / 8);
+        const int kl8 = (q - n * (KC / 8)) * 8;
+        uint16_t* dst = (pl ? a.lo : a.hi) + ((gc * a.kpad + nb0 + n) * KC + kl8);
+        *reinterpret_cast<v4u*>(dst) = *reinterpret_cast<const v4u*>(&sh[pl][n][kl8]);
+    }
+}
+
 // FULL: whole chunks only, unconditional A loads (as in mfma_tile).
-template <int NT, int ADT, int W, bool GEN, bool FULL = false>
+// PK: Omega chunks copied from the call's packed Omega (k_lp_pack) instead of
+// generated or split here; the copy of chunk c + 2 is issued ahead of the A
+// loads of chunk c + 2, so waiting for it leaves those in flight.
+template <int NT, int ADT, int W, bool GEN, bool FULL = false, bool PK = false>
 __device__ __forceinline__ void lp_tile(const MTile& t, uint16_t (*oh)[16 * NT][lp_row(ADT)],
                                         uint16_t (*ol)[16 * NT][lp_row(ADT)]) {
     constexpr int BN = 16 * NT;
@@ -983,13 +1141,43 @@ __device__ __forceinline__ void lp_tile(const MTile& t, uint16_t (*oh)[16 * NT][
     };
 
     // ---- Omega chunk -> LDS as (hi, lo) ------------------------------------------
-    for (int it = tid; it < 2 * BN * lp_row(ADT); it += TH) {
-        const int n = (it / lp_row(ADT)) % BN;
-        if (n >= kb) {
-            (&oh[0][0][0])[it] = 0;
-            (&ol[0][0][0])[it] = 0;
+    if constexpr (!PK) {
+        for (int it = tid; it < 2 * BN * lp_row(ADT); it += TH) {
+            const int n = (it / lp_row(ADT)) % BN;
+            if (n >= kb) {
+                (&oh[0][0][0])[it] = 0;
+                (&ol[0][0][0])[it] = 0;
+            }
         }
     }
+    // packed route: 16-byte pieces of the tile's run of a chunk (both planes),
+    // OPT per thread; chunk indices past the last are clamped (a re-read of
+    // valid memory whose copy lands in the LDS buffer no step reads next)
+    constexpr int PPL = BN * KC / 8;              // pieces per plane
+    constexpr int OPT = (2 * PPL + TH - 1) / TH;
+    auto om_load = [&](v4u* r, int c) {
+        const int cc = c < nchunks ? c : nchunks - 1;
+        const int64_t off = ((t.strip * (kLpStrip / KC) + cc) * t.kpad + t.n_base) * KC;
+#pragma unroll
+        for (int j = 0; j < OPT; ++j) {
+            const int p = min(tid + j * TH, 2 * PPL - 1);
+            const int pl = p >= PPL;
+            const uint16_t* src = (pl ? t.opack_lo : t.opack) + off + (p - pl * PPL) * 8;
+            r[j] = *reinterpret_cast<const v4u*>(src);
+        }
+    };
+    auto om_store = [&](const v4u* r, int c) {
+        const int buf = c & 1;
+#pragma unroll
+        for (int j = 0; j < OPT; ++j) {
+            const int p = min(tid + j * TH, 2 * PPL - 1);
+            const int pl = p >= PPL;
+            const int q = p - pl * PPL;
+            const int n = q / (KC / 8);
+            const int kl8 = (q - n * (KC / 8)) * 8;
+            *reinterpret_cast<v4u*>(pl ? &ol[buf][n][kl8] : &oh[buf][n][kl8]) = r[j];
+        }
+    };
     auto make_chunk = [&](int c) {
         const int buf = c & 1;
         const int kvalid = min(KC, w - c * KC);
@@ -1037,9 +1225,19 @@ __device__ __forceinline__ void lp_tile(const MTile& t, uint16_t (*oh)[16 * NT][
         for (int nt = 0; nt < NT; ++nt) acc[tm][nt] = v4f{0.f, 0.f, 0.f, 0.f};
 
     v4u a0[kTM][RW], a1[kTM][RW];
-    load_a(a0, 0);
-    load_a(a1, 1);
-    make_chunk(0);
+    v4u orr[PK ? OPT : 1];
+    if constexpr (PK) {
+        load_a(a0, 0);
+        om_load(orr, 0);
+        om_store(orr, 0);
+        om_load(orr, 1);
+        __builtin_amdgcn_sched_barrier(0);
+        load_a(a1, 1);
+    } else {
+        load_a(a0, 0);
+        load_a(a1, 1);
+        make_chunk(0);
+    }
     lds_barrier_m();
 
     auto compute = [&](v4u (*a)[RW], int c) {
@@ -1065,7 +1263,26 @@ __device__ __forceinline__ void lp_tile(const MTile& t, uint16_t (*oh)[16 * NT][
         }
     };
 
-    if constexpr (FULL) {
+    if constexpr (PK) {
+        // step c: chunk c + 1's Omega to LDS, chunk c + 2's Omega issued, chunk c's
+        // MFMAs, chunk c + 2's A issued (the same summation order as below)
+        for (int c = 0; c < nchunks; c += 2) {
+            om_store(orr, c + 1);
+            om_load(orr, c + 2);
+            __builtin_amdgcn_sched_barrier(0);
+            compute(a0, c);
+            load_a(a0, c + 2);
+            if constexpr (FULL) __builtin_amdgcn_sched_barrier(0);
+            lds_barrier_m();
+            om_store(orr, c + 2);
+            om_load(orr, c + 3);
+            __builtin_amdgcn_sched_barrier(0);
+            if (c + 1 < nchunks) compute(a1, c + 1);
+            load_a(a1, c + 3);
+            if constexpr (FULL) __builtin_amdgcn_sched_barrier(0);
+            lds_barrier_m();
+        }
+    } else if constexpr (FULL) {
         // the same order with every load issued (and kept ahead of the next chunk's work)
         for (int c = 0; c < nchunks; c += 2) {
             if (c + 1 < nchunks) make_chunk(c + 1);
@@ -1096,18 +1313,26 @@ __device__ __forceinline__ void lp_tile(const MTile& t, uint16_t (*oh)[16 * NT][
     store_tile<NT>(t, acc, row_base, kb, g, i16);
 }
 
-// One call: grid (strips of all blocks, 64W-row tiles, sketch-column blocks).
+// One call: one workgroup per (strip of any block, 64W-row tile, sketch-column
+// block), in the XCD-grouped order of mfma_tile_id.
 // One-N-tile, 4-wave workgroups are kept within 128 registers so that four of
 // them share a compute unit (a 32768-row FP8 launch is exactly four per unit;
 // with three, a quarter of the tiles run as a tail on an underfilled chip).
 constexpr int lp_min_waves(int nt, int w) { return nt == 1 && w == 4 ? 4 : 1; }
 
+// Omega from the call's packed copy with more than one N-tile; one N-tile
+// generates (or splits) its chunks in the tile, as the 128 registers of its
+// 4-wave workgroups hold no staging registers besides.
+constexpr bool lp_packed(int nt) { return nt > 1; }
+
 template <int NT, int ADT, int W, bool GEN, bool FULL>
 __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(lp_min_waves(NT, W))))
 void k_gemm_mfma_lp(const MArgs args) {
-    __shared__ uint16_t oh[2][16 * NT][lp_row(ADT)];
-    __shared__ uint16_t ol[2][16 * NT][lp_row(ADT)];
-    const int strip = blockIdx.x;
+    __shared__ __attribute__((aligned(16))) uint16_t oh[2][16 * NT][lp_row(ADT)];
+    __shared__ __attribute__((aligned(16))) uint16_t ol[2][16 * NT][lp_row(ADT)];
+    TileId id;
+    if (!mfma_tile_id<true>(args, id)) return;
+    const int strip = id.strip;
     int b = 0;
     int64_t sib = strip;
     for (; b < args.P; ++b) {
@@ -1125,8 +1350,8 @@ void k_gemm_mfma_lp(const MArgs args) {
     t.m = args.m;
     t.k = args.k;
     t.col_begin = sib * kLpStrip;
-    t.block_row = (int64_t)blockIdx.y * (64 * W);
-    t.n_base = blockIdx.z * 16 * NT;
+    t.block_row = id.rtile * (64 * W);
+    t.n_base = id.nb * 16 * NT;
     t.key0 = args.key0;
     t.key1 = args.key1;
     t.col0 = args.col0;
@@ -1140,14 +1365,17 @@ void k_gemm_mfma_lp(const MArgs args) {
     t.partials = args.partials;
     t.strip = strip;
     t.single = (args.S_total == 1);
-    lp_tile<NT, ADT, W, GEN, FULL>(t, oh, ol);
+    t.opack = args.opack;
+    t.opack_lo = args.opack_lo;
+    t.kpad = args.kpad;
+    lp_tile<NT, ADT, W, GEN, FULL, lp_packed(NT)>(t, oh, ol);
 }
 
 // Batch of requests of one class (serving); rows per tile = kLpBatchRows.
 template <int NT, int ADT>
 __global__ __launch_bounds__(64 * kLpBatchWaves) void k_gemm_mfma_lp_batch(const BatchArgs args) {
-    __shared__ uint16_t oh[2][16 * NT][lp_row(ADT)];
-    __shared__ uint16_t ol[2][16 * NT][lp_row(ADT)];
+    __shared__ __attribute__((aligned(16))) uint16_t oh[2][16 * NT][lp_row(ADT)];
+    __shared__ __attribute__((aligned(16))) uint16_t ol[2][16 * NT][lp_row(ADT)];
     const int64_t T8 = (args.total_tiles + 7) / 8;
     bool first = true;
     for (int64_t v = blockIdx.x; v < 8 * T8; v += gridDim.x) {   // gridDim.x is a multiple of 8
@@ -1184,6 +1412,9 @@ __global__ __launch_bounds__(64 * kLpBatchWaves) void k_gemm_mfma_lp_batch(const
         t.partials = rq.partials;
         t.strip = strip;
         t.single = (rq.strips == 1);
+        t.opack = nullptr;
+        t.opack_lo = nullptr;
+        t.kpad = 0;
         if (!first) lds_barrier_m();
         first = false;
         lp_tile<NT, ADT, kLpBatchWaves, true>(t, oh, ol);
@@ -1191,8 +1422,10 @@ __global__ __launch_bounds__(64 * kLpBatchWaves) void k_gemm_mfma_lp_batch(const
 }
 
 template <int NT, int ADT, int W, bool GEN>
-hipError_t launch_lp(const MArgs& a, dim3 grid, hipStream_t s) {
-    grid.y = (unsigned)((a.m + 64 * W - 1) / (64 * W));
+hipError_t launch_lp(const MArgs& args, hipStream_t s) {
+    MArgs a = args;
+    a.nrt = (a.m + 64 * W - 1) / (64 * W);
+    const dim3 grid = mfma_grid(a);
     // whole chunks: unconditional loads (one N-tile measured 5-8% slower with them: its
     // 4-wave, 128-register tiles already keep enough loads in flight)
     bool full = NT > 1;
@@ -1205,16 +1438,19 @@ hipError_t launch_lp(const MArgs& a, dim3 grid, hipStream_t s) {
 }
 
 template <int NT, int ADT, bool GEN>
-hipError_t dispatch_lp_w(int waves, const MArgs& a, dim3 grid, hipStream_t s) {
-    return waves == 4 ? launch_lp<NT, ADT, 4, GEN>(a, grid, s) : launch_lp<NT, ADT, 8, GEN>(a, grid, s);
+hipError_t dispatch_lp_w(int waves, const MArgs& a, hipStream_t s) {
+    return waves == 4 ? launch_lp<NT, ADT, 4, GEN>(a, s) : launch_lp<NT, ADT, 8, GEN>(a, s);
 }
 
-template <int ADT, bool GEN>
-hipError_t dispatch_lp(int nt, int waves, const MArgs& a, dim3 grid, hipStream_t s) {
+// packed tiles do not look at GEN (the packing kernel did): one instantiation
+template <int ADT>
+hipError_t dispatch_lp(int nt, bool gen, int waves, const MArgs& a, hipStream_t s) {
+    static_assert(!lp_packed(1) && lp_packed(2) && lp_packed(4), "routes below");
     switch (nt) {
-    case 1: return dispatch_lp_w<1, ADT, GEN>(waves, a, grid, s);
-    case 2: return dispatch_lp_w<2, ADT, GEN>(waves, a, grid, s);
-    default: return dispatch_lp_w<4, ADT, GEN>(waves, a, grid, s);
+    case 1: return gen ? dispatch_lp_w<1, ADT, true>(waves, a, s)
+                       : dispatch_lp_w<1, ADT, false>(waves, a, s);
+    case 2: return dispatch_lp_w<2, ADT, true>(waves, a, s);
+    default: return dispatch_lp_w<4, ADT, true>(waves, a, s);
     }
 }
 
@@ -1267,7 +1503,9 @@ hipError_t launch_gemm_mfma(const GemmLaunch& g) {
     a.y_f64 = g.y_f64;
     a.beta = g.beta;
     for (int b = 0; b < g.P; ++b) a.blk[b] = g.blk[b];
-    const dim3 grid((unsigned)S, (unsigned)((g.m + kBM - 1) / kBM), (unsigned)nblk);
+    a.nrt = (g.m + kBM - 1) / kBM;
+    a.nblk = (int)nblk;
+    const dim3 grid = mfma_grid(a);
     const TraceEvents& tr = g.trace;
     if (tr.begin) (void)hipEventRecord(tr.begin, g.stream);
     hipError_t e = (g.omega == nullptr) ? dispatch_m<true>(nt, a, grid, g.stream)
@@ -1383,13 +1621,67 @@ int lp_waves(int64_t m, int64_t strips, int64_t nblk, int nt) {
     return tiles8 >= device_cus() ? 8 : 4;
 }
 
+namespace {
+
+int64_t lp_kpad(int64_t k) {
+    const int64_t BN = 16 * lp_ntiles(k);
+    return (k + BN - 1) / BN * BN;
+}
+
+// workspace: [strip partials (more than one strip)] [256-B aligned: packed
+// Omega, hi plane then lo plane, strips * kLpStrip * kpad BF16 values each]
+size_t lp_pack_offset(int64_t m, int64_t strips, int64_t k) {
+    return (gemm_workspace_bytes(m, strips, k) + 255) / 256 * 256;
+}
+
+size_t lp_plane_elems(int64_t strips, int64_t k) {
+    return (size_t)strips * (size_t)kLpStrip * (size_t)lp_kpad(k);
+}
+
+template <int ADT>
+hipError_t launch_lp_pack(const PackArgs& p, int64_t strips, hipStream_t s) {
+    const dim3 grid((unsigned)(strips * (kLpStrip / lp_kc(ADT))),
+                    (unsigned)((p.kpad + kPackRows - 1) / kPackRows));
+    if (p.omega)
+        hipLaunchKernelGGL((k_lp_pack<ADT, false>), grid, dim3(256), 0, s, p);
+    else
+        hipLaunchKernelGGL((k_lp_pack<ADT, true>), grid, dim3(256), 0, s, p);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+size_t product_workspace_bytes(int adtype, int64_t m, int64_t strips, int64_t k) {
+    if (!use_mfma_lp(adtype, k) || !lp_packed(lp_ntiles(k))) return gemm_workspace_bytes(m, strips, k);
+    return lp_pack_offset(m, strips, k) + 2 * lp_plane_elems(strips, k) * sizeof(uint16_t);
+}
+
 hipError_t launch_gemm_mfma_lp(const GemmLaunch& g) {
     const int nt = lp_ntiles(g.k);
     const int64_t BN = 16 * nt;
     const int64_t nblk = (g.k + BN - 1) / BN;
     int64_t S = 0;
     for (int b = 0; b < g.P; ++b) S += (g.blk[b].n + kLpStrip - 1) / kLpStrip;
+    PackArgs pk{};
+    if (lp_packed(nt)) {
+        pk.hi = reinterpret_cast<uint16_t*>(static_cast<unsigned char*>(g.workspace) +
+                                            lp_pack_offset(g.m, S, g.k));
+        pk.lo = pk.hi + lp_plane_elems(S, g.k);
+    }
+    pk.k = g.k;
+    pk.kpad = lp_kpad(g.k);
+    pk.key0 = (uint32_t)g.seed;
+    pk.key1 = (uint32_t)(g.seed >> 32);
+    pk.col0 = g.col0;
+    pk.dist = g.dist;
+    pk.omega = g.omega;
+    pk.ldo = g.ldo;
+    pk.P = g.P;
+    for (int b = 0; b < g.P; ++b) pk.blk[b] = g.blk[b];
     MArgs a{};
+    a.opack = pk.hi;
+    a.opack_lo = pk.lo;
+    a.kpad = pk.kpad;
     a.m = g.m;
     a.k = g.k;
     a.ldy = g.ldy;
@@ -1407,17 +1699,17 @@ hipError_t launch_gemm_mfma_lp(const GemmLaunch& g) {
     a.beta = g.beta;
     for (int b = 0; b < g.P; ++b) a.blk[b] = g.blk[b];
     const int waves = lp_waves(g.m, S, nblk, nt);
-    const dim3 grid((unsigned)S, 1u, (unsigned)nblk);
+    a.nblk = (int)nblk;
     const TraceEvents& tr = g.trace;
     if (tr.begin) (void)hipEventRecord(tr.begin, g.stream);
+    hipError_t e = hipSuccess;
+    if (lp_packed(nt)) {
+        e = g.adtype == 1 ? launch_lp_pack<1>(pk, S, g.stream) : launch_lp_pack<2>(pk, S, g.stream);
+        if (e != hipSuccess) return e;
+    }
     const bool gen = (g.omega == nullptr);
-    hipError_t e;
-    if (g.adtype == 1)
-        e = gen ? dispatch_lp<1, true>(nt, waves, a, grid, g.stream)
-                : dispatch_lp<1, false>(nt, waves, a, grid, g.stream);
-    else
-        e = gen ? dispatch_lp<2, true>(nt, waves, a, grid, g.stream)
-                : dispatch_lp<2, false>(nt, waves, a, grid, g.stream);
+    e = g.adtype == 1 ? dispatch_lp<1>(nt, gen, waves, a, g.stream)
+                      : dispatch_lp<2>(nt, gen, waves, a, g.stream);
     if (e != hipSuccess) return e;
     if (tr.mid) (void)hipEventRecord(tr.mid, g.stream);
     if (S > 1) e = launch_reduce_partials(a.partials, (int)S, g.m, g.k, g.Y, g.y_f64, g.ldy,

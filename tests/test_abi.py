@@ -48,7 +48,7 @@ def test_header_symbols_exported():
 
 
 def test_version_and_status_strings():
-    assert sk.sketch_abi_version() == 6
+    assert sk.sketch_abi_version() == 7
     for st in range(-11, 1):
         assert sk.sketch_status_string(st) != "unknown status"
     assert sk.sketch_status_string(-100) == "unknown status"
@@ -353,3 +353,24 @@ def test_nystrom_entry_points_reject_on_host():
     assert rows(row0=-1) == EINVAL and rows(row0=1995) == EINVAL and rows(mr=-1) == EINVAL
     assert rows(out=None) == EINVAL and rows(ldo=1999) == EINVAL and rows(out=PA + 4) == EALIGN
     assert rows(mr=0, out=None) == OK
+
+
+def test_low_precision_workspace_holds_packed_omega():
+    # BF16 / FP8 A with k > 16: the strip partials, then (256-byte aligned) the
+    # call's Omega as hi and lo BF16 planes of S * 4096 * kpad values each
+    ws = sk.sketch_workspace_size
+
+    def packed(m, n, k, P=1, op=0):
+        S = (n + 4095) // 4096 if op == 0 else n // 4096 + P
+        part = S * m * k * 4 if S > 1 else 0
+        kpad = -(-k // (32 if k <= 32 else 64)) * (32 if k <= 32 else 64)
+        return -(-part // 256) * 256 + 2 * S * 4096 * kpad * 2
+
+    for adt in (BF16, FP8):
+        for (m, n, k) in ((32768, 32768, 64), (100, 4096, 17), (300, 5000, 33), (7, 12288, 1000)):
+            assert ws(0, adt, m, n, k, 1) == packed(m, n, k)
+        assert ws(1, adt, 32768, 32768, 64, 8) == packed(32768, 32768, 64, 8, op=1)
+    # one N-tile (k <= 16) forms its Omega inside the tiles: partials only
+    assert ws(0, FP8, 32768, 32768, 5, 1) == 8 * 32768 * 5 * 4
+    assert ws(0, FP8, 100, 4096, 16, 1) == 0
+    assert ws(0, BF16, 100, 4096, 16, 1) == 0
