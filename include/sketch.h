@@ -146,8 +146,9 @@ int sketch_gen_matmul(const void* A, int a_dtype, int64_t m, int64_t n, int64_t 
 /*
  * For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc):
- * sketch_gen_matmul without a workspace argument.  The strip partials go to a
- * fixed device array inside the library, SKETCH_NOALLOC_SCRATCH_BYTES bytes
+ * sketch_gen_matmul without a workspace argument.  What the workspace would
+ * hold (strip partials, packed Omega) goes to a fixed device array inside the
+ * library, SKETCH_NOALLOC_SCRATCH_BYTES bytes
  * per GPU, held from the first call on that GPU until the process ends; the
  * call itself allocates nothing.  Arguments, results and errors are those of
  * sketch_gen_matmul (same kernels, bitwise the same Y), plus SK_ESCRATCH when
