@@ -77,6 +77,7 @@ struct MArgs {
     int64_t kpad;             // sketch columns per packed chunk (k rounded up to the N-tile)
     int64_t nrt;              // row tiles
     int nblk;                 // sketch-column blocks
+    const float* fpack;       // FP32 path with 4+ N-tiles: the call's packed Omega
     BlockDesc blk[kMaxBlocks];
 };
 
@@ -153,6 +154,21 @@ struct MTile {
     const uint16_t* opack;    // packed Omega of the call (low-precision path), hi plane
     const uint16_t* opack_lo; // and lo plane
     int64_t kpad;
+    const float* fpack;       // packed Omega of the call (FP32 path), or nullptr
+};
+
+// Arguments of the kernels that form a call's Omega once, before the product
+// (k_f32_pack: one FP32 plane at hi; k_lp_pack: BF16 hi and lo planes).
+struct PackArgs {
+    void* hi;
+    void* lo;
+    int64_t k, kpad;
+    uint32_t key0, key1, col0;
+    int dist;
+    const float* omega;       // stored Omega (n x k, ldo), or nullptr: generated
+    int64_t ldo;
+    int P;
+    BlockDesc blk[kMaxBlocks];
 };
 
 // Write a wave's accumulators: lane (g, j) holds rows 4g..4g+3 and column j of
@@ -285,13 +301,88 @@ __device__ __forceinline__ void omega_group(const MTile& t, float (*om)[BN][kKC 
     }
 }
 
+// ---- Omega of a whole call for the FP32 tiles (four or more N-tiles) ---------
+// As for the low-precision route: every 512-row tile of a strip multiplies the
+// same Omega chunks, so the call forms them once.  One FP32 plane, chunk
+// gc = strip * (kMfmaStrip / 32) + c, then sketch column n in [0, kpad), then
+// contraction column kl in [0, 32): element (gc * kpad + n) * 32 + kl; the
+// values (zeros past the strip's end and for n >= k) are those omega_chunk
+// writes into LDS, so the sums are the same bit for bit.
+constexpr int kF32PackRows = 16;   // sketch columns per packing workgroup
+constexpr bool mfma_packed(int nt) { return nt >= 4; }
+
+// grid (chunks of all strips, ceil(kpad / 16)); 256 threads
+template <bool GEN>
+__global__ __launch_bounds__(256) void k_f32_pack(const PackArgs a) {
+    constexpr int KC = chunk_cols(4);
+    constexpr int CPS = kMfmaStrip / KC;
+    __shared__ __attribute__((aligned(16))) float sh[kF32PackRows][KC + 4];
+    const int tid = threadIdx.x;
+    const int64_t gc = blockIdx.x;
+    const int64_t strip = gc / CPS;
+    const int c = (int)(gc - strip * CPS);
+    int b = 0;
+    int64_t sib = strip;
+    for (; b < a.P; ++b) {
+        const int64_t sb = (a.blk[b].n + kMfmaStrip - 1) / kMfmaStrip;
+        if (sib < sb) break;
+        sib -= sb;
+    }
+    const int64_t col_begin = sib * kMfmaStrip;
+    const int w = (int)min<int64_t>(kMfmaStrip, a.blk[b].n - col_begin);
+    if (c * KC >= w) return;                      // past the strip's end: never read
+    const int kvalid = min(KC, w - c * KC);
+    const int nb0 = blockIdx.y * kF32PackRows;
+    const int kb = (int)min<int64_t>(kF32PackRows, a.k - nb0);   // <= 0: all zero
+    for (int it = tid; it < kF32PackRows * (KC + 4); it += 256) (&sh[0][0])[it] = 0.0f;
+    __syncthreads();
+    if constexpr (GEN) {
+        const int64_t g0 = a.blk[b].row0 + col_begin + (int64_t)c * KC;
+        const int64_t q_lo = g0 >> 2;
+        const int nq = (int)(((g0 + KC - 1) >> 2) - q_lo + 1);
+        const int items = kb > 0 ? nq * kb : 0;
+        for (int it = tid; it < items; it += 256) {
+            const int qi = it / kb;
+            const int n = it - qi * kb;
+            const float4 z = omega4_dist((uint64_t)(q_lo + qi), a.col0 + (uint32_t)(nb0 + n),
+                                         a.key0, a.key1, a.dist);
+            const int kl0 = (int)(4 * (q_lo + qi) - g0);
+            const float zz[4] = {z.x, z.y, z.z, z.w};
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int kl = kl0 + u;
+                if (kl >= 0 && kl < kvalid) sh[n][kl] = zz[u];
+            }
+        }
+    } else {
+        const int items = kb > 0 ? kvalid * kb : 0;
+        for (int it = tid; it < items; it += 256) {
+            const int kl = it / kb;
+            const int n = it - kl * kb;
+            sh[n][kl] = a.omega[(col_begin + (int64_t)c * KC + kl) * a.ldo + nb0 + n];
+        }
+    }
+    __syncthreads();
+    const int rows = (int)min<int64_t>(kF32PackRows, a.kpad - nb0);
+    float* out = static_cast<float*>(a.hi);
+    for (int it = tid; it < rows * (KC / 4); it += 256) {
+        const int n = it / (KC / 4);
+        const int kl4 = (it - n * (KC / 4)) * 4;
+        *reinterpret_cast<v4f*>(out + ((gc * a.kpad + nb0 + n) * KC + kl4)) =
+            *reinterpret_cast<const v4f*>(&sh[n][kl4]);
+    }
+}
+
 // FULL: every chunk of the launch is whole (block widths multiples of the chunk
 // width).  Then every lane issues the same A loads every chunk, unconditionally
 // (a load past the strip's end re-reads its last chunk, never used), and the
 // compiler waits for the chunk being multiplied alone; with the per-lane tail
 // path present it waits for every load in flight, including the next chunk's,
 // which undoes the double buffering.
-template <int NT, bool GEN, bool FULL = false>
+// PK: Omega chunks copied from the call's packed Omega (k_f32_pack); the copy of
+// chunk c + 2 is issued ahead of the A loads issued after it, so waiting for
+// it leaves those in flight.
+template <int NT, bool GEN, bool FULL = false, bool PK = false>
 __device__ __forceinline__ void mfma_tile(const MTile& t, float (*om)[16 * NT][lds_row(NT)]) {
     constexpr int BN = 16 * NT;
     constexpr int kKC = chunk_cols(NT);
@@ -349,8 +440,32 @@ __device__ __forceinline__ void mfma_tile(const MTile& t, float (*om)[16 * NT][l
     };
 
     // ---- Omega chunk -> LDS ----------------------------------------------------------
-    omega_zero_pad<BN, kKC>(om, kb);
+    if constexpr (!PK) omega_zero_pad<BN, kKC>(om, kb);
     auto make_chunk = [&](int c) { omega_chunk<BN, kKC, GEN>(t, om, c, w, kb); };
+    // packed route: 16-byte pieces of the tile's run of a chunk, OPT per thread;
+    // chunk indices past the last are clamped (a re-read of valid memory whose
+    // copy lands in the LDS half no step reads next)
+    constexpr int PPL = BN * kKC / 4;
+    constexpr int OPT = (PPL + kThreads - 1) / kThreads;
+    auto om_load = [&](v4f* r, int c) {
+        const int cc = c < nchunks ? c : nchunks - 1;
+        const float* src = t.fpack + ((t.strip * (kMfmaStrip / kKC) + cc) * t.kpad + n_base) * kKC;
+#pragma unroll
+        for (int j = 0; j < OPT; ++j) {
+            const int p = min(tid + j * kThreads, PPL - 1);
+            r[j] = *reinterpret_cast<const v4f*>(src + 4 * p);
+        }
+    };
+    auto om_store = [&](const v4f* r, int c) {
+        const int buf = c & 1;
+#pragma unroll
+        for (int j = 0; j < OPT; ++j) {
+            const int p = min(tid + j * kThreads, PPL - 1);
+            const int n = p / (kKC / 4);
+            const int kl4 = (p - n * (kKC / 4)) * 4;
+            *reinterpret_cast<v4f*>(&om[buf][n][kl4]) = r[j];
+        }
+    };
 
     v4f acc[kTM][NT];
 #pragma unroll
@@ -359,9 +474,21 @@ __device__ __forceinline__ void mfma_tile(const MTile& t, float (*om)[16 * NT][l
         for (int nt = 0; nt < NT; ++nt) acc[tm][nt] = v4f{0.f, 0.f, 0.f, 0.f};
 
     v4f a0[kTM][kLV], a1[kTM][kLV];
-    load_a(a0, 0);
-    if constexpr (!single_a(NT)) load_a(a1, 1);
-    make_chunk(0);
+    v4f orr[PK ? OPT : 1];
+    if constexpr (PK) {
+        load_a(a0, 0);
+        om_load(orr, 0);
+        om_store(orr, 0);
+        if constexpr (!single_a(NT)) {
+            om_load(orr, 1);
+            __builtin_amdgcn_sched_barrier(0);
+            load_a(a1, 1);
+        }
+    } else {
+        load_a(a0, 0);
+        if constexpr (!single_a(NT)) load_a(a1, 1);
+        make_chunk(0);
+    }
     lds_barrier_m();
 
     auto compute = [&](v4f (*a)[kLV], int c) {
@@ -383,7 +510,36 @@ __device__ __forceinline__ void mfma_tile(const MTile& t, float (*om)[16 * NT][l
         }
     };
 
-    if constexpr (single_a(NT)) {
+    if constexpr (PK && single_a(NT)) {
+        // one A buffer (the accumulators leave no room for more): step c runs
+        // chunk c's MFMAs, then issues chunk c + 1's A and Omega loads and
+        // stores the Omega copy (its registers are never live across MFMAs);
+        // the next step needs those A loads at once either way
+        for (int c = 0; c < nchunks; ++c) {
+            compute(a0, c);
+            load_a(a0, c + 1);
+            om_load(orr, c + 1);
+            om_store(orr, c + 1);
+            lds_barrier_m();
+        }
+    } else if constexpr (PK) {
+        for (int c = 0; c < nchunks; c += 2) {
+            om_store(orr, c + 1);
+            om_load(orr, c + 2);
+            __builtin_amdgcn_sched_barrier(0);
+            compute(a0, c);
+            load_a(a0, c + 2);
+            if constexpr (FULL) __builtin_amdgcn_sched_barrier(0);
+            lds_barrier_m();
+            om_store(orr, c + 2);
+            om_load(orr, c + 3);
+            __builtin_amdgcn_sched_barrier(0);
+            if (c + 1 < nchunks) compute(a1, c + 1);
+            load_a(a1, c + 3);
+            if constexpr (FULL) __builtin_amdgcn_sched_barrier(0);
+            lds_barrier_m();
+        }
+    } else if constexpr (single_a(NT)) {
         for (int c = 0; c < nchunks; ++c) {
             if (c + 1 < nchunks) make_chunk(c + 1);
             compute(a0, c);
@@ -450,8 +606,9 @@ __global__ __launch_bounds__(kThreads) void k_gemm_mfma(const MArgs args) {
     t.single = (args.S_total == 1);
     t.opack = nullptr;
     t.opack_lo = nullptr;
-    t.kpad = 0;
-    mfma_tile<NT, GEN, FULL>(t, om);
+    t.kpad = args.kpad;
+    t.fpack = args.fpack;
+    mfma_tile<NT, GEN, FULL, mfma_packed(NT)>(t, om);
 }
 
 // A batch of independent requests (serving): the tiles of each request are the
@@ -499,6 +656,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm_mfma_batch(const BatchArgs ar
         t.opack = nullptr;
         t.opack_lo = nullptr;
         t.kpad = 0;
+        t.fpack = nullptr;
         if (!first) lds_barrier_m();   // every wave is done with the previous tile's LDS
         first = false;
         mfma_tile<NT, true>(t, om);
@@ -968,17 +1126,6 @@ __device__ __forceinline__ void fp8x4_to_bf16(uint32_t w, uint32_t& lo2, uint32_
 // then one contiguous run of BN * KC values.  Entries past the strip's last
 // column and sketch columns >= k hold zero; the values are those the fused
 // generation writes into LDS, so both routes give the same sums bit for bit.
-struct PackArgs {
-    uint16_t* hi;
-    uint16_t* lo;
-    int64_t k, kpad;
-    uint32_t key0, key1, col0;
-    int dist;
-    const float* omega;       // stored Omega (n x k, ldo), or nullptr: generated
-    int64_t ldo;
-    int P;
-    BlockDesc blk[kMaxBlocks];
-};
 
 // sketch columns per packing workgroup: 16 gives each compute unit several
 // workgroups to interleave (the work is a chain of dependent arithmetic)
@@ -1047,7 +1194,7 @@ __global__ __launch_bounds__(256) void k_lp_pack(const PackArgs a) {
         const int q = it - pl * pieces;
         const int n = q / (KC / 8);
         const int kl8 = (q - n * (KC / 8)) * 8;
-        uint16_t* dst = (pl ? a.lo : a.hi) + ((gc * a.kpad + nb0 + n) * KC + kl8);
+        uint16_t* dst = static_cast<uint16_t*>(pl ? a.lo : a.hi) + ((gc * a.kpad + nb0 + n) * KC + kl8);
         *reinterpret_cast<v4u*>(dst) = *reinterpret_cast<const v4u*>(&sh[pl][n][kl8]);
     }
 }
@@ -1368,6 +1515,7 @@ void k_gemm_mfma_lp(const MArgs args) {
     t.opack = args.opack;
     t.opack_lo = args.opack_lo;
     t.kpad = args.kpad;
+    t.fpack = nullptr;
     lp_tile<NT, ADT, W, GEN, FULL, lp_packed(NT)>(t, oh, ol);
 }
 
@@ -1415,6 +1563,7 @@ __global__ __launch_bounds__(64 * kLpBatchWaves) void k_gemm_mfma_lp_batch(const
         t.opack = nullptr;
         t.opack_lo = nullptr;
         t.kpad = 0;
+        t.fpack = nullptr;
         if (!first) lds_barrier_m();
         first = false;
         lp_tile<NT, ADT, kLpBatchWaves, true>(t, oh, ol);
@@ -1456,12 +1605,14 @@ hipError_t dispatch_lp(int nt, bool gen, int waves, const MArgs& a, hipStream_t 
 
 template <int NT, bool GEN>
 hipError_t launch_m(const MArgs& a, dim3 grid, hipStream_t s) {
+    // packed tiles do not look at GEN (the packing kernel did): one instantiation
+    constexpr bool G = mfma_packed(NT) || GEN;
     bool full = true;
     for (int b = 0; b < a.P; ++b) full = full && a.blk[b].n % chunk_cols(NT) == 0;
     if (full)
-        hipLaunchKernelGGL((k_gemm_mfma<NT, GEN, true>), grid, dim3(kThreads), 0, s, a);
+        hipLaunchKernelGGL((k_gemm_mfma<NT, G, true>), grid, dim3(kThreads), 0, s, a);
     else
-        hipLaunchKernelGGL((k_gemm_mfma<NT, GEN, false>), grid, dim3(kThreads), 0, s, a);
+        hipLaunchKernelGGL((k_gemm_mfma<NT, G, false>), grid, dim3(kThreads), 0, s, a);
     return hipGetLastError();
 }
 
@@ -1480,13 +1631,48 @@ hipError_t dispatch_m(int nt, const MArgs& a, dim3 grid, hipStream_t s) {
 // N-tiles (of 16 sketch columns) per workgroup for a sketch of width k.
 int mfma_ntiles(int64_t k) { return k <= 16 ? 1 : k <= 32 ? 2 : k <= 64 ? 4 : 8; }
 
+namespace {
+
+// workspace of a packed route: [strip partials (more than one strip)]
+// [256-B aligned: the packed Omega planes]
+size_t pack_offset(int64_t m, int64_t strips, int64_t k) {
+    return (gemm_workspace_bytes(m, strips, k) + 255) / 256 * 256;
+}
+
+int64_t mfma_kpad(int64_t k) {
+    const int64_t BN = 16 * mfma_ntiles(k);
+    return (k + BN - 1) / BN * BN;
+}
+
+size_t f32_plane_elems(int64_t strips, int64_t k) {
+    return (size_t)strips * (size_t)kMfmaStrip * (size_t)mfma_kpad(k);
+}
+
+}  // namespace
+
 hipError_t launch_gemm_mfma(const GemmLaunch& g) {
     const int nt = mfma_ntiles(g.k);
     const int64_t BN = 16 * nt;
     const int64_t nblk = (g.k + BN - 1) / BN;
     int64_t S = 0;
     for (int b = 0; b < g.P; ++b) S += (g.blk[b].n + kMfmaStrip - 1) / kMfmaStrip;
+    PackArgs pk{};
+    if (mfma_packed(nt)) {
+        pk.hi = static_cast<unsigned char*>(g.workspace) + pack_offset(g.m, S, g.k);
+        pk.k = g.k;
+        pk.kpad = mfma_kpad(g.k);
+        pk.key0 = (uint32_t)g.seed;
+        pk.key1 = (uint32_t)(g.seed >> 32);
+        pk.col0 = g.col0;
+        pk.dist = g.dist;
+        pk.omega = g.omega;
+        pk.ldo = g.ldo;
+        pk.P = g.P;
+        for (int b = 0; b < g.P; ++b) pk.blk[b] = g.blk[b];
+    }
     MArgs a{};
+    a.fpack = static_cast<const float*>(pk.hi);
+    a.kpad = pk.kpad;
     a.m = g.m;
     a.k = g.k;
     a.ldy = g.ldy;
@@ -1508,6 +1694,16 @@ hipError_t launch_gemm_mfma(const GemmLaunch& g) {
     const dim3 grid = mfma_grid(a);
     const TraceEvents& tr = g.trace;
     if (tr.begin) (void)hipEventRecord(tr.begin, g.stream);
+    if (mfma_packed(nt)) {
+        const dim3 pgrid((unsigned)(S * (kMfmaStrip / chunk_cols(nt))),
+                         (unsigned)((pk.kpad + kF32PackRows - 1) / kF32PackRows));
+        if (pk.omega)
+            hipLaunchKernelGGL((k_f32_pack<false>), pgrid, dim3(256), 0, g.stream, pk);
+        else
+            hipLaunchKernelGGL((k_f32_pack<true>), pgrid, dim3(256), 0, g.stream, pk);
+        const hipError_t pe = hipGetLastError();
+        if (pe != hipSuccess) return pe;
+    }
     hipError_t e = (g.omega == nullptr) ? dispatch_m<true>(nt, a, grid, g.stream)
                                         : dispatch_m<false>(nt, a, grid, g.stream);
     if (e != hipSuccess) return e;
@@ -1628,12 +1824,8 @@ int64_t lp_kpad(int64_t k) {
     return (k + BN - 1) / BN * BN;
 }
 
-// workspace: [strip partials (more than one strip)] [256-B aligned: packed
-// Omega, hi plane then lo plane, strips * kLpStrip * kpad BF16 values each]
-size_t lp_pack_offset(int64_t m, int64_t strips, int64_t k) {
-    return (gemm_workspace_bytes(m, strips, k) + 255) / 256 * 256;
-}
-
+// packed Omega after the partials (pack_offset): hi plane then lo plane,
+// strips * kLpStrip * kpad BF16 values each
 size_t lp_plane_elems(int64_t strips, int64_t k) {
     return (size_t)strips * (size_t)kLpStrip * (size_t)lp_kpad(k);
 }
@@ -1652,8 +1844,11 @@ hipError_t launch_lp_pack(const PackArgs& p, int64_t strips, hipStream_t s) {
 }  // namespace
 
 size_t product_workspace_bytes(int adtype, int64_t m, int64_t strips, int64_t k) {
-    if (!use_mfma_lp(adtype, k) || !lp_packed(lp_ntiles(k))) return gemm_workspace_bytes(m, strips, k);
-    return lp_pack_offset(m, strips, k) + 2 * lp_plane_elems(strips, k) * sizeof(uint16_t);
+    if (use_mfma(adtype, k) && mfma_packed(mfma_ntiles(k)))
+        return pack_offset(m, strips, k) + f32_plane_elems(strips, k) * sizeof(float);
+    if (use_mfma_lp(adtype, k) && lp_packed(lp_ntiles(k)))
+        return pack_offset(m, strips, k) + 2 * lp_plane_elems(strips, k) * sizeof(uint16_t);
+    return gemm_workspace_bytes(m, strips, k);
 }
 
 hipError_t launch_gemm_mfma_lp(const GemmLaunch& g) {
@@ -1664,9 +1859,10 @@ hipError_t launch_gemm_mfma_lp(const GemmLaunch& g) {
     for (int b = 0; b < g.P; ++b) S += (g.blk[b].n + kLpStrip - 1) / kLpStrip;
     PackArgs pk{};
     if (lp_packed(nt)) {
-        pk.hi = reinterpret_cast<uint16_t*>(static_cast<unsigned char*>(g.workspace) +
-                                            lp_pack_offset(g.m, S, g.k));
-        pk.lo = pk.hi + lp_plane_elems(S, g.k);
+        uint16_t* hi = reinterpret_cast<uint16_t*>(static_cast<unsigned char*>(g.workspace) +
+                                                   pack_offset(g.m, S, g.k));
+        pk.hi = hi;
+        pk.lo = hi + lp_plane_elems(S, g.k);
     }
     pk.k = g.k;
     pk.kpad = lp_kpad(g.k);
@@ -1679,8 +1875,8 @@ hipError_t launch_gemm_mfma_lp(const GemmLaunch& g) {
     pk.P = g.P;
     for (int b = 0; b < g.P; ++b) pk.blk[b] = g.blk[b];
     MArgs a{};
-    a.opack = pk.hi;
-    a.opack_lo = pk.lo;
+    a.opack = static_cast<const uint16_t*>(pk.hi);
+    a.opack_lo = static_cast<const uint16_t*>(pk.lo);
     a.kpad = pk.kpad;
     a.m = g.m;
     a.k = g.k;

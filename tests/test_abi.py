@@ -229,12 +229,18 @@ def test_workspace_size_rules():
     assert b >= (8 + 8) * 32768 * 5 * 4                 # bound valid for any 8-way split
     assert ws(2, F32, 1, 1, 1, 1) == 0 and ws(0, 5, 1, 1, 1, 1) == 0 and ws(1, F32, 1, 1, 1, 0) == 0
     assert ws(0, F32, 100, 5000, 1025, 1) == 0          # k > 1024 is invalid
-    assert ws(0, F32, 100, 5000, 1024, 1) == 3 * 100 * 1024 * 4   # 2048-column strips
+    # 2048-column strips; k > 32 on the FP32 matrix cores adds the call's packed
+    # Omega (S * 2048 * kpad floats) after the 256-byte aligned partials
+    assert ws(0, F32, 100, 5000, 1024, 1) == 3 * 100 * 1024 * 4 + 3 * 2048 * 1024 * 4
     # FP32 on the VALU path (k <= 8): 4096-column strips at every k; the matrix-core
     # path (FP32, k > 8) uses 2048-column strips
     assert ws(0, F32, 4096, 32768, 8, 1) == 8 * 4096 * 8 * 4
     assert ws(0, F32, 4096, 32768, 9, 1) == 16 * 4096 * 9 * 4
     assert ws(0, F32, 4096, 32768, 17, 1) == 16 * 4096 * 17 * 4
+    assert ws(0, F32, 4096, 32768, 32, 1) == 16 * 4096 * 32 * 4        # two N-tiles: no packing
+    assert ws(0, F32, 4096, 32768, 33, 1) == 16 * 4096 * 33 * 4 + 16 * 2048 * 64 * 4
+    assert ws(0, F32, 100, 2048, 64, 1) == 2048 * 64 * 4                # one strip: packing only
+    assert ws(0, F32, 7, 32768, 65, 1) == -(-16 * 7 * 65 * 4 // 256) * 256 + 16 * 2048 * 128 * 4
     assert sk.sketch_strip_width(F32, 5) == 4096 and sk.sketch_strip_width(F32, 8) == 4096
     assert sk.sketch_strip_width(F32, 9) == 2048 and sk.sketch_strip_width(F32, 17) == 2048
     # FP8 at every k and BF16 past 8 columns: BF16 matrix cores, 4096-column strips

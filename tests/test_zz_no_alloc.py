@@ -77,6 +77,7 @@ def test_noalloc_full_scratch_then_smaller():
     L = sk.lib()
     n, k = 32768, 64                       # matrix cores: 16 strips of 2048 columns
     per_row = L.sketch_workspace_size(0, 0, 2, n, k, 1) - L.sketch_workspace_size(0, 0, 1, n, k, 1)
-    m = SCRATCH // per_row
+    base = L.sketch_workspace_size(0, 0, 1, n, k, 1) - per_row    # the packed Omega
+    m = (SCRATCH - base) // per_row
     assert L.sketch_workspace_size(0, 0, m, n, k, 1) <= SCRATCH
     _pair([((m, n), 0), ((1000, 5000), 11)], k, torch.float32)
