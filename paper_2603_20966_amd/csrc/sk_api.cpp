@@ -88,7 +88,7 @@ size_t sketch_workspace_size(int op, int a_dtype, int64_t m, int64_t n, int64_t 
         return 0;
     if (op == 2) {   // column-major A (sketch_gen_matmul_cm; sketch_gen_tmatmul with m = p)
         if (a_dtype != SK_A_F32 || m == 0 || k == 0 || n == 0) return 0;
-        return sk::gemm_workspace_bytes(m, sk::cm_strips(n, k), k);
+        return sk::cm_workspace_bytes(m, n, k);
     }
     if (op == 0) P = 1;
     if (P < 1 || P > sk::kMaxBlocks || m == 0 || k == 0 || n == 0) return 0;
@@ -302,7 +302,7 @@ int sketch_gen_matmul_cm(const float* A, int64_t m, int64_t n, int64_t lda, uint
     const int64_t S = n > 0 ? sk::cm_strips(n, k) : 0;
     const int64_t tiles = S * ((m + 255) / 256) * ((k + sk::kColGroup - 1) / sk::kColGroup);
     if (tiles > ((int64_t)1 << 31) - 8) return SK_EUNSUPPORTED;
-    int st = check_workspace(S > 1 ? sk::gemm_workspace_bytes(m, S, k) : 0, workspace,
+    int st = check_workspace(n > 0 ? sk::cm_workspace_bytes(m, n, k) : 0, workspace,
                              workspace_bytes);
     if (st != SK_OK) return st;
     const hipStream_t s = static_cast<hipStream_t>(stream);

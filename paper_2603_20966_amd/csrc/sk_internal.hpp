@@ -136,6 +136,8 @@ size_t gemm_workspace_bytes(int64_t m, int64_t strips, int64_t k);
 // Workspace of a product call over `strips` strips: the strip partials, and on
 // the low-precision matrix-core route the call's packed Omega after them.
 size_t product_workspace_bytes(int adtype, int64_t m, int64_t strips, int64_t k);
+// Workspace of a column-major product call (m rows, n contraction columns).
+size_t cm_workspace_bytes(int64_t m, int64_t n, int64_t k);
 
 // Column-major A (element (i, j) at A + j*lda + i), FP32, generated Omega; Y
 // row-major or transposed (element (i, c) at Y + c*ldy + i).  Strips of

@@ -688,6 +688,8 @@ struct CmMArgs {
     int S;                 // strips of kMfmaStrip columns
     int num_rb;            // 512-row tiles
     int64_t tiles, tiles8;
+    const float* fpack;    // four or more N-tiles: the call's packed Omega (k_f32_pack)
+    int64_t kpad;
 };
 
 // KC = the row-major kernel's chunk for this k (chunk_cols(mfma_ntiles(k))),
@@ -696,6 +698,10 @@ struct CmMArgs {
 // loads each chunk from a valid address (a lane or wave without rows reads row 0;
 // its sums are never stored; a load past the strip's end re-reads its last chunk),
 // so the compiler waits for the chunk in use alone (see mfma_tile).
+// Packed Omega on the column-major tiles: four or more N-tiles, except eight
+// without whole chunks (that kernel's registers have no room for the copy).
+constexpr bool cm_packed(int nt, bool full) { return mfma_packed(nt) && (full || nt < 8); }
+
 template <int NT, int kKC, bool FULL>
 __global__ __launch_bounds__(kThreads) void k_gemm_cm_mfma(const CmMArgs a) {
     constexpr int BN = 16 * NT;
@@ -761,7 +767,31 @@ __global__ __launch_bounds__(kThreads) void k_gemm_cm_mfma(const CmMArgs a) {
         }
     };
 
-    omega_zero_pad<BN, kKC>(om, kb);
+    // packed route (as mfma_tile): 16-byte pieces of the tile's run of a chunk
+    constexpr bool PK = cm_packed(NT, FULL);
+    constexpr int PPL = BN * kKC / 4;
+    constexpr int OPT = (PPL + kThreads - 1) / kThreads;
+    const int tid = threadIdx.x;
+    auto om_load = [&](v4f* r, int c) {
+        const int cc = c < nchunks ? c : nchunks - 1;
+        const float* src = a.fpack + (((int64_t)strip * (kMfmaStrip / kKC) + cc) * a.kpad + t.n_base) * kKC;
+#pragma unroll
+        for (int i = 0; i < OPT; ++i) {
+            const int p = min(tid + i * kThreads, PPL - 1);
+            r[i] = *reinterpret_cast<const v4f*>(src + 4 * p);
+        }
+    };
+    auto om_store = [&](const v4f* r, int slot) {
+#pragma unroll
+        for (int i = 0; i < OPT; ++i) {
+            const int p = min(tid + i * kThreads, PPL - 1);
+            const int n = p / (kKC / 4);
+            const int kl4 = (p - n * (kKC / 4)) * 4;
+            *reinterpret_cast<v4f*>(&om[slot][n][kl4]) = r[i];
+        }
+    };
+
+    if constexpr (!PK) omega_zero_pad<BN, kKC>(om, kb);
     v4f acc[4][NT];
 #pragma unroll
     for (int q = 0; q < 4; ++q)
@@ -769,9 +799,22 @@ __global__ __launch_bounds__(kThreads) void k_gemm_cm_mfma(const CmMArgs a) {
         for (int nt = 0; nt < NT; ++nt) acc[q][nt] = v4f{0.f, 0.f, 0.f, 0.f};
 
     v4f a0[kNS], a1[kNS];
-    load_a(a0, 0);
-    if constexpr (!single_a(NT)) load_a(a1, 1);
-    omega_group<BN, kKC, kG>(t, om, 0, 0, nchunks, w, kb);
+    v4f orr[PK ? OPT : 1];
+    if constexpr (PK) {
+        static_assert(!PK || kG == 1, "one chunk per barrier on the packed route");
+        load_a(a0, 0);
+        om_load(orr, 0);
+        om_store(orr, 0);
+        if constexpr (!single_a(NT)) {
+            om_load(orr, 1);
+            __builtin_amdgcn_sched_barrier(0);
+            load_a(a1, 1);
+        }
+    } else {
+        load_a(a0, 0);
+        if constexpr (!single_a(NT)) load_a(a1, 1);
+        omega_group<BN, kKC, kG>(t, om, 0, 0, nchunks, w, kb);
+    }
     lds_barrier_m();
 
     auto compute = [&](const v4f* x, int buf) {
@@ -794,7 +837,33 @@ __global__ __launch_bounds__(kThreads) void k_gemm_cm_mfma(const CmMArgs a) {
                             wop[nt][v][s], x[4 * v + s][q], acc[q][nt], 0, 0, 0);
     };
 
-    if constexpr (single_a(NT)) {
+    if constexpr (PK && single_a(NT)) {
+        // the order of mfma_tile's packed loops (Omega copies never live across MFMAs here)
+        for (int c = 0; c < nchunks; ++c) {
+            compute(a0, c & 1);
+            load_a(a0, c + 1);
+            om_load(orr, c + 1);
+            om_store(orr, (c + 1) & 1);
+            lds_barrier_m();
+        }
+    } else if constexpr (PK) {
+        for (int c = 0; c < nchunks; c += 2) {
+            om_store(orr, 1);
+            om_load(orr, c + 2);
+            __builtin_amdgcn_sched_barrier(0);
+            compute(a0, 0);
+            load_a(a0, c + 2);
+            if constexpr (FULL) __builtin_amdgcn_sched_barrier(0);
+            lds_barrier_m();
+            om_store(orr, 0);
+            om_load(orr, c + 3);
+            __builtin_amdgcn_sched_barrier(0);
+            if (c + 1 < nchunks) compute(a1, 1);
+            load_a(a1, c + 3);
+            if constexpr (FULL) __builtin_amdgcn_sched_barrier(0);
+            lds_barrier_m();
+        }
+    } else if constexpr (single_a(NT)) {
         for (int c = 0; c < nchunks; ++c) {
             if (c + 1 < nchunks) omega_group<BN, kKC, 1>(t, om, (c + 1) & 1, c + 1, nchunks, w, kb);
             compute(a0, c & 1);
@@ -1782,6 +1851,27 @@ hipError_t launch_gemm_cm_mfma(const CmLaunch& g) {
     a.tiles = (int64_t)a.S * a.num_rb * ((g.k + BN - 1) / BN);
     a.tiles8 = (a.tiles + 7) / 8;
     hipError_t e;
+    constexpr int KCc = chunk_cols(8);
+    if (!skinny && cm_packed(nt, g.m % 4 == 0 && g.n % KCc == 0)) {
+        // the call's Omega, once (the same plane as the row-major call's)
+        PackArgs pk{};
+        pk.hi = static_cast<unsigned char*>(g.workspace) + pack_offset(g.m, S, g.k);
+        pk.k = g.k;
+        pk.kpad = mfma_kpad(g.k);
+        pk.key0 = a.key0;
+        pk.key1 = a.key1;
+        pk.col0 = a.col0;
+        pk.dist = a.dist;
+        pk.P = 1;
+        pk.blk[0] = BlockDesc{g.A, g.n, g.lda, g.row0, nullptr};
+        const dim3 pgrid((unsigned)(S * (kMfmaStrip / chunk_cols(nt))),
+                         (unsigned)((pk.kpad + kF32PackRows - 1) / kF32PackRows));
+        hipLaunchKernelGGL((k_f32_pack<true>), pgrid, dim3(256), 0, g.stream, pk);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        a.fpack = static_cast<const float*>(pk.hi);
+        a.kpad = pk.kpad;
+    }
     constexpr int KC = chunk_cols(8);
     static_assert(chunk_cols(1) == KC && chunk_cols(2) == KC && chunk_cols(4) == KC,
                   "one chunk width for every N-tile count of the row-major kernel");
@@ -1842,6 +1932,15 @@ hipError_t launch_lp_pack(const PackArgs& p, int64_t strips, hipStream_t s) {
 }
 
 }  // namespace
+
+// column-major A: partials, and the packed Omega where the tile kernel takes it
+// (k > 32 and more rows than the few-row kernels take; the launch may still run
+// fewer N-tiles and leave it unused)
+size_t cm_workspace_bytes(int64_t m, int64_t n, int64_t k) {
+    const int64_t S = cm_strips(n, k);
+    if (k <= kColGroup || m <= 64) return gemm_workspace_bytes(m, S, k);
+    return product_workspace_bytes(0, m, S, k);
+}
 
 size_t product_workspace_bytes(int adtype, int64_t m, int64_t strips, int64_t k) {
     if (use_mfma(adtype, k) && mfma_packed(mfma_ntiles(k)))

@@ -253,6 +253,9 @@ def test_workspace_size_rules():
     assert ws(2, F32, 300, 5000, 17, 1) == 3 * 300 * 17 * 4
     assert ws(2, F32, 64, 2048, 64, 1) == 0               # one 2048 strip: Y written directly
     assert ws(2, F32, 64, 32768, 256, 1) == 16 * 64 * 256 * 4
+    # more than 64 rows and k > 32: the tile kernel's packed Omega after the partials
+    assert ws(2, F32, 300, 32768, 64, 1) == 16 * 300 * 64 * 4 + 16 * 2048 * 64 * 4
+    assert ws(2, F32, 65, 2048, 33, 1) == 2048 * 64 * 4
 
 
 def test_python_binding_requires_library(monkeypatch, tmp_path):
