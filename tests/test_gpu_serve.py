@@ -252,3 +252,30 @@ def test_request_validation():
             srv.submit(r)
         with pytest.raises(sk.SketchError):
             srv.poll(12345)
+
+
+def test_packed_omega_route_equals_in_tile_generation():
+    """Direct calls with k > 32 (FP32) or k > 16 (BF16/FP8) first pack the call's Omega
+    and copy it into the tiles; the server's batched kernels generate each chunk inside
+    the tile.  Whole-chunk widths (the unconditional-load kernels) and ragged rows: both
+    routes give the same bits."""
+    f32 = [(520, 4096, 40), (1030, 8192, 64), (600, 6144, 128), (300, 4096, 300)]
+    lp = [("bf16", 700, 8192, 64), ("fp8", 513, 8192, 64), ("bf16", 129, 4096, 20),
+          ("fp8", 1024, 4096, 100)]
+    reqs = []
+    for i, (m, n, k) in enumerate(f32):
+        A = dev_matrix(m, n, seed=80 + i)[1]
+        reqs.append((A, None, k, sk.sketch_gen_matmul(A, 90 + i, k)))
+    for i, (kind, m, n, k) in enumerate(lp):
+        Aq, sc = sk.sketch_quantize(dev_matrix(m, n, seed=85 + i)[1], kind)
+        reqs.append((Aq, sc, k, sk.sketch_gen_matmul(Aq, 95 + i, k, a_scales=sc)))
+    seeds = [90 + i for i in range(len(f32))] + [95 + i for i in range(len(lp))]
+    Ys = [torch.full((A.shape[0], k), float("nan"), device=DEV) for A, _, k, _ in reqs]
+    torch.cuda.synchronize()
+    with sk.SketchServer(1 << 30, max_slots=8, max_batch=8) as srv:
+        ts = [srv.submit(sv.make_request(A=A, k=k, seed=s, Y=Y, a_scales=sc), A, sc, Y)
+              for (A, sc, k, _), Y, s in zip(reqs, Ys, seeds)]
+        infos = [srv.wait(t, 60.0) for t in ts]
+    assert all(x["state"] == sv.SK_REQ_DONE and x["status"] == 0 for x in infos), infos
+    for (A, sc, k, Yd), Y in zip(reqs, Ys):
+        assert torch.equal(Y, Yd), (A.dtype, A.shape, k)
