@@ -1896,13 +1896,13 @@ hipError_t launch_gemm_cm_mfma(const CmLaunch& g) {
 
 int lp_ntiles(int64_t k) { return k <= 16 ? 1 : k <= 32 ? 2 : 4; }
 
-// Waves per workgroup of the low-precision kernel.  With one N-tile the Omega
-// chunk is small and 4-wave workgroups win (several per compute unit, whose
-// chunk phases do not line up: measured 3.2 vs 2.6 TB/s for FP8 at k = 5);
-// with more N-tiles generation dominates and 8 waves share each chunk (k = 64:
-// 1.7 vs 1.2 TB/s for FP8), unless that leaves compute units without a tile.
+// Waves per workgroup of the low-precision kernel: 8 (512 rows share each
+// Omega chunk), unless that leaves compute units without a tile.  Measured on
+// 32768^2 with the XCD-grouped tile order: FP8 k = 5 199-201 us against 207-210
+// with 4-wave workgroups, k = 64 299 against 375.  (Before that order, 4-wave
+// workgroups had won at k = 5: 3.2 vs 2.6 TB/s.)
 int lp_waves(int64_t m, int64_t strips, int64_t nblk, int nt) {
-    if (nt == 1) return 4;
+    (void)nt;
     const int64_t tiles8 = strips * ((m + 511) / 512) * nblk;
     return tiles8 >= device_cus() ? 8 : 4;
 }
