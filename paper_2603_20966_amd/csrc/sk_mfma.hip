@@ -984,10 +984,27 @@ __global__ __launch_bounds__(kThreads) void k_gemm_cm_mfma_skinny(const CmMArgs 
         if (n >= kb) (&om[0][0][0])[it] = 0.0f;
     }
     // chunks of group gi -> slots (gi & 1) * kSkG .. ; same values and layout as the
-    // tile kernel's chunks (zeros past the strip's end)
+    // tile kernel's chunks (zeros past the strip's end).  With the call's packed
+    // Omega (a.fpack) the generating waves copy them: 16-byte pieces, chunks past
+    // the last clamped to it (their slots are never read).
     const int64_t gb = a.row0 + col_begin;
     const int nq = (int)(((gb + kKC - 1) >> 2) - (gb >> 2) + 1);   // quads per chunk
     auto gen_group = [&](int gi) {
+        if (a.fpack) {
+            constexpr int PPC = BN * kKC / 4;                   // pieces per chunk
+            for (int it = threadIdx.x - kGenThreads; it < kSkG * PPC; it += kGenThreads) {
+                const int ci = it / PPC;
+                const int pc = it - ci * PPC;
+                const int c = min(gi * kSkG + ci, nchunks - 1);
+                const int n = pc / (kKC / 4);
+                const int kl4 = (pc - n * (kKC / 4)) * 4;
+                const float* src = a.fpack +
+                    (((int64_t)strip * (kMfmaStrip / kKC) + c) * a.kpad + n_base + n) * kKC + kl4;
+                *reinterpret_cast<v4f*>(&om[(gi & 1) * kSkG + ci][n][kl4]) =
+                    *reinterpret_cast<const v4f*>(src);
+            }
+            return;
+        }
         const int c0 = gi * kSkG;
         const int cnt = min(kSkG, nchunks - c0);
         const int per = nq * kb;
@@ -1852,8 +1869,9 @@ hipError_t launch_gemm_cm_mfma(const CmLaunch& g) {
     a.tiles8 = (a.tiles + 7) / 8;
     hipError_t e;
     constexpr int KCc = chunk_cols(8);
-    if (!skinny && cm_packed(nt, g.m % 4 == 0 && g.n % KCc == 0)) {
-        // the call's Omega, once (the same plane as the row-major call's)
+    if (skinny || cm_packed(nt, g.m % 4 == 0 && g.n % KCc == 0)) {
+        // the call's Omega, once (the same plane as the row-major call's); the
+        // few-row kernel copies it instead of generating in its workgroups
         PackArgs pk{};
         pk.hi = static_cast<unsigned char*>(g.workspace) + pack_offset(g.m, S, g.k);
         pk.k = g.k;
@@ -1933,12 +1951,13 @@ hipError_t launch_lp_pack(const PackArgs& p, int64_t strips, hipStream_t s) {
 
 }  // namespace
 
-// column-major A: partials, and the packed Omega where the tile kernel takes it
-// (k > 32 and more rows than the few-row kernels take; the launch may still run
-// fewer N-tiles and leave it unused)
+// column-major A: partials, and the packed Omega where a matrix-core kernel
+// takes it: the few-row kernel (m <= 64) at every k > 16, the tile kernel at
+// k > 32 (whose launch may still run fewer N-tiles and leave it unused)
 size_t cm_workspace_bytes(int64_t m, int64_t n, int64_t k) {
     const int64_t S = cm_strips(n, k);
-    if (k <= kColGroup || m <= 64) return gemm_workspace_bytes(m, S, k);
+    if (k <= kColGroup) return gemm_workspace_bytes(m, S, k);
+    if (m <= 64) return pack_offset(m, S, k) + f32_plane_elems(S, k) * sizeof(float);
     return product_workspace_bytes(0, m, S, k);
 }
 

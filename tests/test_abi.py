@@ -251,8 +251,11 @@ def test_workspace_size_rules():
     assert ws(2, F32, 300, 5000, 5, 1) == 5 * 300 * 5 * 4
     assert ws(2, F32, 300, 5000, 16, 1) == 5 * 300 * 16 * 4
     assert ws(2, F32, 300, 5000, 17, 1) == 3 * 300 * 17 * 4
-    assert ws(2, F32, 64, 2048, 64, 1) == 0               # one 2048 strip: Y written directly
-    assert ws(2, F32, 64, 32768, 256, 1) == 16 * 64 * 256 * 4
+    # few rows (m <= 64) past k = 16: the few-row kernel copies the call's packed
+    # Omega (one 2048 strip: no partials, Y written directly)
+    assert ws(2, F32, 64, 2048, 64, 1) == 2048 * 64 * 4
+    assert ws(2, F32, 5, 4096, 17, 1) == 768 + 2 * 2048 * 32 * 4     # 680 B of partials, aligned
+    assert ws(2, F32, 64, 32768, 256, 1) == 16 * 64 * 256 * 4 + 16 * 2048 * 256 * 4
     # more than 64 rows and k > 32: the tile kernel's packed Omega after the partials
     assert ws(2, F32, 300, 32768, 64, 1) == 16 * 300 * 64 * 4 + 16 * 2048 * 64 * 4
     assert ws(2, F32, 65, 2048, 33, 1) == 2048 * 64 * 4
