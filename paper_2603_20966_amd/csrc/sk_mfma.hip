@@ -311,16 +311,22 @@ __device__ __forceinline__ void omega_group(const MTile& t, float (*om)[BN][kKC 
 constexpr int kF32PackRows = 16;   // sketch columns per packing workgroup
 constexpr bool mfma_packed(int nt) { return nt >= 4; }
 
-// grid (chunks of all strips, ceil(kpad / 16)); 256 threads
+// grid (chunks of all strips / kF32PackChunks, ceil(kpad / 16)); 256 threads.
+// A workgroup forms kF32PackChunks consecutive chunks of one strip (a strip is
+// 64 chunks), so that its threads have Philox quads enough to keep busy.
+constexpr int kF32PackChunks = 4;
+
 template <bool GEN>
 __global__ __launch_bounds__(256) void k_f32_pack(const PackArgs a) {
     constexpr int KC = chunk_cols(4);
     constexpr int CPS = kMfmaStrip / KC;
-    __shared__ __attribute__((aligned(16))) float sh[kF32PackRows][KC + 4];
+    constexpr int G = kF32PackChunks;
+    static_assert(CPS % G == 0, "groups of chunks inside a strip");
+    __shared__ __attribute__((aligned(16))) float sh[G][kF32PackRows][KC + 4];
     const int tid = threadIdx.x;
-    const int64_t gc = blockIdx.x;
-    const int64_t strip = gc / CPS;
-    const int c = (int)(gc - strip * CPS);
+    const int64_t gc0 = (int64_t)blockIdx.x * G;          // first chunk of the group
+    const int64_t strip = gc0 / CPS;
+    const int c0 = (int)(gc0 - strip * CPS);
     int b = 0;
     int64_t sib = strip;
     for (; b < a.P; ++b) {
@@ -330,20 +336,25 @@ __global__ __launch_bounds__(256) void k_f32_pack(const PackArgs a) {
     }
     const int64_t col_begin = sib * kMfmaStrip;
     const int w = (int)min<int64_t>(kMfmaStrip, a.blk[b].n - col_begin);
-    if (c * KC >= w) return;                      // past the strip's end: never read
-    const int kvalid = min(KC, w - c * KC);
+    const int nc = min(G, (w - c0 * KC + KC - 1) / KC);   // chunks of the group inside the strip
+    if (nc <= 0) return;                                  // past the strip's end: never read
     const int nb0 = blockIdx.y * kF32PackRows;
     const int kb = (int)min<int64_t>(kF32PackRows, a.k - nb0);   // <= 0: all zero
-    for (int it = tid; it < kF32PackRows * (KC + 4); it += 256) (&sh[0][0])[it] = 0.0f;
+    for (int it = tid; it < G * kF32PackRows * (KC + 4); it += 256) (&sh[0][0][0])[it] = 0.0f;
     __syncthreads();
     if constexpr (GEN) {
-        const int64_t g0 = a.blk[b].row0 + col_begin + (int64_t)c * KC;
-        const int64_t q_lo = g0 >> 2;
-        const int nq = (int)(((g0 + KC - 1) >> 2) - q_lo + 1);
-        const int items = kb > 0 ? nq * kb : 0;
-        for (int it = tid; it < items; it += 256) {
-            const int qi = it / kb;
-            const int n = it - qi * kb;
+        // every chunk starts at the same offset within a Philox quad (KC is a multiple of 4)
+        const int64_t gs = a.blk[b].row0 + col_begin + (int64_t)c0 * KC;
+        const int nq = (int)(((gs + KC - 1) >> 2) - (gs >> 2) + 1);
+        const int per = kb > 0 ? nq * kb : 0;
+        for (int it = tid; it < nc * per; it += 256) {
+            const int ci = it / per;
+            const int r = it - ci * per;
+            const int qi = r / kb;
+            const int n = r - qi * kb;
+            const int64_t g0 = gs + (int64_t)ci * KC;
+            const int kvalid = min(KC, w - (c0 + ci) * KC);
+            const int64_t q_lo = g0 >> 2;
             const float4 z = omega4_dist((uint64_t)(q_lo + qi), a.col0 + (uint32_t)(nb0 + n),
                                          a.key0, a.key1, a.dist);
             const int kl0 = (int)(4 * (q_lo + qi) - g0);
@@ -351,25 +362,31 @@ __global__ __launch_bounds__(256) void k_f32_pack(const PackArgs a) {
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int kl = kl0 + u;
-                if (kl >= 0 && kl < kvalid) sh[n][kl] = zz[u];
+                if (kl >= 0 && kl < kvalid) sh[ci][n][kl] = zz[u];
             }
         }
     } else {
-        const int items = kb > 0 ? kvalid * kb : 0;
-        for (int it = tid; it < items; it += 256) {
-            const int kl = it / kb;
-            const int n = it - kl * kb;
-            sh[n][kl] = a.omega[(col_begin + (int64_t)c * KC + kl) * a.ldo + nb0 + n];
+        const int per = kb > 0 ? KC * kb : 0;
+        for (int it = tid; it < nc * per; it += 256) {
+            const int ci = it / per;
+            const int r = it - ci * per;
+            const int kl = r / kb;
+            const int n = r - kl * kb;
+            if (kl < min(KC, w - (c0 + ci) * KC))
+                sh[ci][n][kl] = a.omega[(col_begin + (int64_t)(c0 + ci) * KC + kl) * a.ldo + nb0 + n];
         }
     }
     __syncthreads();
     const int rows = (int)min<int64_t>(kF32PackRows, a.kpad - nb0);
+    const int ppc = rows * (KC / 4);                      // 16-byte pieces per chunk
     float* out = static_cast<float*>(a.hi);
-    for (int it = tid; it < rows * (KC / 4); it += 256) {
-        const int n = it / (KC / 4);
-        const int kl4 = (it - n * (KC / 4)) * 4;
-        *reinterpret_cast<v4f*>(out + ((gc * a.kpad + nb0 + n) * KC + kl4)) =
-            *reinterpret_cast<const v4f*>(&sh[n][kl4]);
+    for (int it = tid; it < nc * ppc; it += 256) {
+        const int ci = it / ppc;
+        const int pc = it - ci * ppc;
+        const int n = pc / (KC / 4);
+        const int kl4 = (pc - n * (KC / 4)) * 4;
+        *reinterpret_cast<v4f*>(out + (((gc0 + ci) * a.kpad + nb0 + n) * KC + kl4)) =
+            *reinterpret_cast<const v4f*>(&sh[ci][n][kl4]);
     }
 }
 
@@ -1781,7 +1798,7 @@ hipError_t launch_gemm_mfma(const GemmLaunch& g) {
     const TraceEvents& tr = g.trace;
     if (tr.begin) (void)hipEventRecord(tr.begin, g.stream);
     if (mfma_packed(nt)) {
-        const dim3 pgrid((unsigned)(S * (kMfmaStrip / chunk_cols(nt))),
+        const dim3 pgrid((unsigned)(S * (kMfmaStrip / chunk_cols(nt)) / kF32PackChunks),
                          (unsigned)((pk.kpad + kF32PackRows - 1) / kF32PackRows));
         if (pk.omega)
             hipLaunchKernelGGL((k_f32_pack<false>), pgrid, dim3(256), 0, g.stream, pk);
@@ -1882,7 +1899,7 @@ hipError_t launch_gemm_cm_mfma(const CmLaunch& g) {
         pk.dist = a.dist;
         pk.P = 1;
         pk.blk[0] = BlockDesc{g.A, g.n, g.lda, g.row0, nullptr};
-        const dim3 pgrid((unsigned)(S * (kMfmaStrip / chunk_cols(nt))),
+        const dim3 pgrid((unsigned)(S * (kMfmaStrip / chunk_cols(nt)) / kF32PackChunks),
                          (unsigned)((pk.kpad + kF32PackRows - 1) / kF32PackRows));
         hipLaunchKernelGGL((k_f32_pack<true>), pgrid, dim3(256), 0, g.stream, pk);
         e = hipGetLastError();
