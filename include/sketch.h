@@ -100,13 +100,19 @@ const char* sketch_status_string(int status);
 int64_t sketch_strip_width(int a_dtype, int64_t k);
 
 /* Bytes of device workspace a call needs (0 if none).  The workspace holds
- * the FP32 partial sums of the column strips between the streaming kernel and
- * the FP64 reduction kernel of one call (more than one strip), and, for BF16
- * or FP8 A with k > 16, the call's Omega as two BF16 planes (the hi and lo
- * terms of each entry, 2 * S * 4096 * kpad values, S strips, kpad = k rounded
- * up to a multiple of 32 for k <= 32, of 64 beyond), formed by the call
- * itself at a 256-byte aligned offset after the partials.  Its contents need
- * no preparation.
+ * the FP32 partial sums of the column strips between the product kernel and
+ * the FP64 reduction kernel of one call (more than one strip), and, on the
+ * matrix-core routes that multiply every strip's Omega chunks in several row
+ * tiles, the call's Omega formed once by the call itself, at a 256-byte
+ * aligned offset after the partials:
+ *   BF16 or FP8 A with k > 16: two BF16 planes (the hi and lo terms of each
+ *     entry), 2 * S * 4096 * kpad values, kpad = k rounded up to a multiple
+ *     of 32 for k <= 32, of 64 beyond;
+ *   FP32 A with k > 32 (op 0 and 1), and column-major FP32 A with k > 32, or
+ *     with k > 16 and m <= 64 (op 2): one FP32 plane of S * 2048 * kpad
+ *     values, kpad = k rounded up to a multiple of 16 * nt, nt = 1, 2, 4, 8
+ *     for k <= 16, 32, 64 and beyond;
+ * S the call's strips.  Its contents need no preparation.
  * One workspace serves one call at a time: calls that may run concurrently
  * (different streams) need separate workspaces.
  *   op = 0: sketch_gen_matmul / sketch_matmul_omega with an n-column A;
