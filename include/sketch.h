@@ -3,9 +3,11 @@
  *
  *     Y = A * Omega(seed)
  *
- * where Omega is a dense N(0,1) random matrix that is never stored: every
- * call regenerates the entries it needs from a 64-bit seed with a
- * counter-based Philox4x32-10 generator, inside the multiply kernel.
+ * where Omega is a dense N(0,1) random matrix that is never communicated or
+ * kept between calls: every call regenerates the entries it needs from a
+ * 64-bit seed with a counter-based Philox4x32-10 generator on the device,
+ * inside the multiply kernel or, on the matrix-core routes whose row tiles
+ * share Omega chunks, once per call into the call's workspace.
  *
  * Paper: "Communication Lower Bounds and Algorithms for Sketching with Random
  * Dense Matrices" (SPAA '26).
