@@ -198,16 +198,19 @@ __global__ __launch_bounds__(256) void k_gemm_cm(const CmArgs a) {
 // narrow sketch): the tile above would leave all but m/4 lanes of one wave
 // idle and walk each wave's 256 columns of a strip one load round at a time.
 // Here a workgroup takes one strip and one group of sketch columns; all its
-// threads stage the strip's columns of A (all 1024 at once for m <= 8 and
+// kSkinnyThreads threads stage the strip's columns of A (all 1024 at once for m <= 8 and
 // k <= 8, else 256 at a time) and their Omega rows in LDS, and thread (w, i, c) runs the chain that wave w of the tile kernel
-// runs for row i and sketch column c: columns j = w, w + 4, ... of the strip
-// in order, FP32 fma, then the four chains added in wave order.  Every sum is
-// the tile kernel's, bit for bit.
+// runs for row i and sketch column c (waves 0..3): columns j = w, w + 4, ... of
+// the strip in order, FP32 fma, then the four chains added in wave order.  Every
+// sum is the tile kernel's, bit for bit.  The other twelve waves only help stage:
+// with four waves the Philox work of a strip (1280 quads at k = 5) ran five quads
+// deep per thread with nothing to hide its latency.
 constexpr int kSkinnyRows = 16;
+constexpr int kSkinnyThreads = 1024;
 
 // SUB strip columns staged per step, MP rows (LDS pitch of a column).
 template <int K, int SUB, int MP>
-__global__ __launch_bounds__(256) void k_gemm_cm_skinny(const CmArgs a) {
+__global__ __launch_bounds__(kSkinnyThreads) void k_gemm_cm_skinny(const CmArgs a) {
     constexpr int C = cm_strip_width(K);
     constexpr int KP = (K + 3) / 4 * 4;
     constexpr int CQ = (K + 3) / 4;                    // sketch columns per thread
@@ -219,7 +222,8 @@ __global__ __launch_bounds__(256) void k_gemm_cm_skinny(const CmArgs a) {
     const int strip = (int)(blockIdx.x % a.S);
     const int cg = (int)(blockIdx.x / a.S);
     const int tid = threadIdx.x;
-    const int wave = tid >> 6;                         // chain: columns j = wave (mod 4)
+    const int wave = tid >> 6;                         // chain (waves 0..3): columns j = wave (mod 4)
+    const bool chain = wave < 4;
     const int i = (tid & 63) >> 2;                     // row
     const int cq = tid & 3;                            // sketch columns cq, cq + 4, ...
     const int64_t col_begin = (int64_t)strip * C;
@@ -239,7 +243,7 @@ __global__ __launch_bounds__(256) void k_gemm_cm_skinny(const CmArgs a) {
         const int64_t g0 = a.row0 + col_begin + js;
         const int64_t q_lo = g0 >> 2;
         const int nq = (int)(((g0 + sw - 1) >> 2) - q_lo + 1);
-        for (int it = tid; it < nq * kg; it += 256) {
+        for (int it = tid; it < nq * kg; it += kSkinnyThreads) {
             const int qi = it / kg;
             const int c = it - qi * kg;
             const float4 z = omega4_dist((uint64_t)(q_lo + qi), a.col0 + (uint32_t)(c_base + c),
@@ -251,12 +255,12 @@ __global__ __launch_bounds__(256) void k_gemm_cm_skinny(const CmArgs a) {
                 if (j >= 0 && j < sw) om[j * KP + c] = zz[u];
             }
         }
-        for (int e = tid; e < sw * m; e += 256) {
+        for (int e = tid; e < sw * m; e += kSkinnyThreads) {
             const int j = e / m, r = e - j * m;
             as[j * MP + r] = a.A[(col_begin + js + j) * a.lda + r];
         }
         lds_barrier_c();
-        if (i < m) {
+        if (chain && i < m) {
             // the chain over columns j = wave (mod 4) of this step, in order (js is a
             // multiple of 4); 8 columns' LDS reads are issued ahead of their fmas
             auto step = [&](int j) {
@@ -287,7 +291,7 @@ __global__ __launch_bounds__(256) void k_gemm_cm_skinny(const CmArgs a) {
         lds_barrier_c();
     }
 
-    if (wave > 0 && i < m) {
+    if (chain && wave > 0 && i < m) {
 #pragma unroll
         for (int u = 0; u < CQ; ++u) hand[wave - 1][i][cq + 4 * u] = acc[u];
     }
@@ -326,12 +330,13 @@ hipError_t launch_cm_k(const CmArgs& a, hipStream_t s) {
         const dim3 grid((unsigned)(a.S * ((a.k + kColGroup - 1) / kColGroup)));
         if constexpr (K <= 8) {
             if (a.m <= 8) {
-                hipLaunchKernelGGL((k_gemm_cm_skinny<K, cm_strip_width(K), 8>), grid, dim3(256), 0,
-                                   s, a);
+                hipLaunchKernelGGL((k_gemm_cm_skinny<K, cm_strip_width(K), 8>), grid, dim3(kSkinnyThreads),
+                                   0, s, a);
                 return hipGetLastError();
             }
         }
-        hipLaunchKernelGGL((k_gemm_cm_skinny<K, 256, kSkinnyRows>), grid, dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_gemm_cm_skinny<K, 256, kSkinnyRows>), grid, dim3(kSkinnyThreads), 0, s,
+                           a);
         return hipGetLastError();
     }
     hipLaunchKernelGGL((k_gemm_cm<K>), dim3((unsigned)(8 * a.tiles8)), dim3(256), 0, s, a);
