@@ -215,8 +215,13 @@ __global__ __launch_bounds__(kSkinnyThreads) void k_gemm_cm_skinny(const CmArgs 
     constexpr int KP = (K + 3) / 4 * 4;
     constexpr int CQ = (K + 3) / 4;                    // sketch columns per thread
     static_assert(MP <= kSkinnyRows && C % SUB == 0 && SUB % 4 == 0, "staging geometry");
-    __shared__ __attribute__((aligned(16))) float om[SUB * KP];
-    __shared__ float as[SUB * MP];                     // as[j * MP + i] = A(i, j)
+    // Staged by chain: column j of the step sits in the block of wave j % 4, at
+    // position j / 4 of a row of pitch PJ (4 floats of padding keep the rows of one
+    // wave's reads on different banks), so a chain's 8 columns of a batch are two
+    // 16-byte LDS reads
+    constexpr int PJ = SUB / 4 + 4;
+    __shared__ __attribute__((aligned(16))) float om[4 * KP * PJ];   // [j % 4][c][j / 4]
+    __shared__ __attribute__((aligned(16))) float as[4 * MP * PJ];   // [j % 4][i][j / 4] = A(i, j)
     __shared__ float hand[3][MP][4 * CQ];
 
     const int strip = (int)(blockIdx.x % a.S);
@@ -252,33 +257,43 @@ __global__ __launch_bounds__(kSkinnyThreads) void k_gemm_cm_skinny(const CmArgs 
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int64_t j = 4 * (q_lo + qi) + u - g0;
-                if (j >= 0 && j < sw) om[j * KP + c] = zz[u];
+                if (j >= 0 && j < sw) om[((j & 3) * KP + c) * PJ + (j >> 2)] = zz[u];
             }
         }
         for (int e = tid; e < sw * m; e += kSkinnyThreads) {
             const int j = e / m, r = e - j * m;
-            as[j * MP + r] = a.A[(col_begin + js + j) * a.lda + r];
+            as[((j & 3) * MP + r) * PJ + (j >> 2)] = a.A[(col_begin + js + j) * a.lda + r];
         }
         lds_barrier_c();
         if (chain && i < m) {
             // the chain over columns j = wave (mod 4) of this step, in order (js is a
-            // multiple of 4); 8 columns' LDS reads are issued ahead of their fmas
+            // multiple of 4); a batch of 8 columns is read before its fmas
+            const float* xa = &as[(wave * MP + i) * PJ];
+            const float* oa[CQ];
+#pragma unroll
+            for (int u = 0; u < CQ; ++u) oa[u] = &om[(wave * KP + min(cq + 4 * u, KP - 1)) * PJ];
             auto step = [&](int j) {
-                const float x = as[j * MP + i];
+                const float x = xa[j >> 2];
 #pragma unroll
                 for (int u = 0; u < CQ; ++u) {
                     const int c = cq + 4 * u;
-                    if (c < kg) acc[u] = __builtin_fmaf(x, om[j * KP + c], acc[u]);
+                    if (c < kg) acc[u] = __builtin_fmaf(x, oa[u][j >> 2], acc[u]);
                 }
             };
             int j = wave;
             for (; j + 28 < sw; j += 32) {
+                const int b = j >> 2;                  // a multiple of 8 (wave < 4)
                 float x[8], o[8][CQ];
+                const v4f x0 = *reinterpret_cast<const v4f*>(xa + b);
+                const v4f x1 = *reinterpret_cast<const v4f*>(xa + b + 4);
 #pragma unroll
-                for (int t = 0; t < 8; ++t) {
-                    x[t] = as[(j + 4 * t) * MP + i];
+                for (int t = 0; t < 4; ++t) { x[t] = x0[t]; x[t + 4] = x1[t]; }
 #pragma unroll
-                    for (int u = 0; u < CQ; ++u) o[t][u] = om[(j + 4 * t) * KP + min(cq + 4 * u, KP - 1)];
+                for (int u = 0; u < CQ; ++u) {
+                    const v4f o0 = *reinterpret_cast<const v4f*>(oa[u] + b);
+                    const v4f o1 = *reinterpret_cast<const v4f*>(oa[u] + b + 4);
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) { o[t][u] = o0[t]; o[t + 4][u] = o1[t]; }
                 }
 #pragma unroll
                 for (int t = 0; t < 8; ++t)
