@@ -958,14 +958,15 @@ __global__ __launch_bounds__(kThreads) void k_gemm_cm_mfma(const CmMArgs a) {
 
 // Few rows (m <= 64; e.g. B^T of the Nystrom second product): the kernel above
 // gives a tile's 64 rows to one wave, which runs all 4 x NT accumulator chains
-// while the other seven idle, and the Omega generation then waits on the
-// chains.  Here a workgroup takes one strip and one N-tile of 16 sketch
-// columns, and its waves split the work: waves 0..3 each run one chain (row
-// set q = wave: rows 4j + q of lane j) with the steps, operands and order of
+// while the other seven idle.  Here a workgroup takes one strip and one N-tile of
+// 16 sketch columns, and its waves split the work: waves 0..3 each run one chain
+// (row set q = wave: rows 4j + q of lane j) with the steps, operands and order of
 // the kernel above, so the results equal it (and the row-major kernel) bit for
-// bit; waves 4..7 generate the Omega chunks, kSkG chunks per barrier, into the
-// other half of a double-buffered LDS ring.
-constexpr int kSkG = 8;
+// bit; waves 4..7 stage kSkG chunks at a time, A and the call's packed Omega,
+// into the other half of a double-buffered LDS ring, with the loads of the group
+// after next in flight while they store the next one.  A chain's step then waits
+// on LDS only, not on a global load.
+constexpr int kSkG = 4;
 
 template <int kKC, bool ALIGNED>
 __global__ __launch_bounds__(kThreads) void k_gemm_cm_mfma_skinny(const CmMArgs a) {
@@ -973,7 +974,15 @@ __global__ __launch_bounds__(kThreads) void k_gemm_cm_mfma_skinny(const CmMArgs 
     constexpr int kNS = kKC / 4;
     constexpr int kLV = kKC / 16;
     constexpr int kGenThreads = kThreads / 2;
-    __shared__ float om[2 * kSkG][BN][kKC + 4];
+    // a staged column of A: row 4j + q at [q][j], 2 floats of padding so that the
+    // four lane groups of a chain's read (8 columns apart) fall on different banks
+    constexpr int kAP = 66;
+    constexpr int kAPieces = kSkG * kKC * 16 / kGenThreads;       // 16-byte pieces of A per thread
+    constexpr int kOPieces = kSkG * BN * kKC / 4 / kGenThreads;   // and of Omega
+    static_assert(kAPieces * kGenThreads == kSkG * kKC * 16 &&
+                  kOPieces * kGenThreads == kSkG * BN * kKC / 4, "whole pieces per thread");
+    __shared__ __attribute__((aligned(16))) float om[2 * kSkG][BN][kKC + 4];
+    __shared__ float as[2 * kSkG][kKC][kAP];
 
     const int64_t tt = blockIdx.x;
     if (tt >= a.tiles) return;
@@ -993,142 +1002,126 @@ __global__ __launch_bounds__(kThreads) void k_gemm_cm_mfma_skinny(const CmMArgs 
     const int ngroups = (nchunks + kSkG - 1) / kSkG;
     const int kb = (int)min<int64_t>(BN, a.k - n_base);
     const int64_t rl = 4 * j;                               // first row of the lane
-    const bool full_rows = rl + 3 < a.m;
 
-    // columns past k of every slot are zero (generation writes columns < kb only)
+    // columns past k of every slot are zero (the packed plane holds zeros there too)
     for (int it = threadIdx.x; it < 2 * kSkG * BN * (kKC + 4); it += kThreads) {
         const int n = (it / (kKC + 4)) % BN;
         if (n >= kb) (&om[0][0][0])[it] = 0.0f;
     }
-    // chunks of group gi -> slots (gi & 1) * kSkG .. ; same values and layout as the
-    // tile kernel's chunks (zeros past the strip's end).  With the call's packed
-    // Omega (a.fpack) the generating waves copy them: 16-byte pieces, chunks past
-    // the last clamped to it (their slots are never read).
-    const int64_t gb = a.row0 + col_begin;
-    const int nq = (int)(((gb + kKC - 1) >> 2) - (gb >> 2) + 1);   // quads per chunk
-    auto gen_group = [&](int gi) {
-        if (a.fpack) {
-            constexpr int PPC = BN * kKC / 4;                   // pieces per chunk
-            for (int it = threadIdx.x - kGenThreads; it < kSkG * PPC; it += kGenThreads) {
-                const int ci = it / PPC;
-                const int pc = it - ci * PPC;
-                const int c = min(gi * kSkG + ci, nchunks - 1);
-                const int n = pc / (kKC / 4);
-                const int kl4 = (pc - n * (kKC / 4)) * 4;
-                const float* src = a.fpack +
-                    (((int64_t)strip * (kMfmaStrip / kKC) + c) * a.kpad + n_base + n) * kKC + kl4;
-                *reinterpret_cast<v4f*>(&om[(gi & 1) * kSkG + ci][n][kl4]) =
-                    *reinterpret_cast<const v4f*>(src);
-            }
-            return;
-        }
-        const int c0 = gi * kSkG;
-        const int cnt = min(kSkG, nchunks - c0);
-        const int per = nq * kb;
-        for (int it = threadIdx.x - kGenThreads; it < cnt * per; it += kGenThreads) {
-            const int ci = it / per;
-            const int r = it - ci * per;
-            const int qi = r / kb;
-            const int n = r - qi * kb;
-            const int c = c0 + ci;
-            const int64_t g0 = gb + (int64_t)c * kKC;
-            const int kvalid = min(kKC, w - c * kKC);
-            const int64_t qq = (g0 >> 2) + qi;
-            const float4 z = omega4_dist((uint64_t)qq, a.col0 + (uint32_t)(n_base + n), a.key0,
-                                         a.key1, a.dist);
-            const int kl0 = (int)(4 * qq - g0);
-            float* dst = om[(gi & 1) * kSkG + ci][n];
-            const float zz[4] = {z.x, z.y, z.z, z.w};
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int kl = kl0 + u;
-                if (kl >= 0 && kl < kKC) dst[kl] = (kl < kvalid) ? zz[u] : 0.0f;
-            }
-        }
-    };
 
-    // ALIGNED (m a multiple of 4): every lane issues the same loads from a valid
-    // address (a lane without rows reads row 0: its sums are never stored; a column
-    // past the strip reads the strip's last column and is zeroed when its chunk is
-    // used), so the compiler can wait for each ring buffer alone instead of for every
-    // load in flight
-    const bool has_rows = rl < a.m;
-    const float* acol = a.A + (col_begin + g * kNS) * a.lda + (ALIGNED && !has_rows ? 0 : rl);
-    auto load_a = [&](v4f* x, int c) {
-        if constexpr (ALIGNED) {
-            c = min(c, nchunks - 1);          // past the end: the last chunk again, never used
-        } else {
-            if (c >= nchunks) return;
-        }
-        const int kl = c * kKC + g * kNS;
+    // staging (waves 4..7).  Every load is issued unconditionally from a valid
+    // address (chunks past the strip's last re-read it, rows past m read rows 0..3,
+    // columns past the strip's end read its last column), so the compiler waits for
+    // the older group only; columns past the strip's end are stored as zeros, rows
+    // past m are never stored by the chains.
+    const int tg = threadIdx.x - kGenThreads;
+    auto g_load = [&](int gi, v4f* xa, v4f* xo) {
 #pragma unroll
-        for (int s = 0; s < kNS; ++s) {
+        for (int t = 0; t < kAPieces; ++t) {
+            const int p = tg + t * kGenThreads;
+            const int ci = p / (kKC * 16);
+            const int rem = p - ci * (kKC * 16);
+            const int col = rem >> 4;
+            const int r4 = rem & 15;
+            const int c = min(gi * kSkG + ci, nchunks - 1);
+            const int64_t colg = col_begin + min(c * kKC + col, w - 1);
+            const float* src = a.A + colg * a.lda;
             if constexpr (ALIGNED) {
-                const int cl = min(kl + s, w - 1) - g * kNS;     // column offset from acol
-                x[s] = *reinterpret_cast<const v4f*>(acol + (int64_t)cl * a.lda);
+                xa[t] = *reinterpret_cast<const v4f*>(src + (4 * r4 < a.m ? 4 * r4 : 0));
             } else {
-                const float* p = acol + (int64_t)(c * kKC + s) * a.lda;
-                if (full_rows && kl + s < w) {
-                    x[s] = *reinterpret_cast<const v4f*>(p);
+                v4f v = {0.f, 0.f, 0.f, 0.f};
+                if (4 * r4 + 3 < a.m) {
+                    v = *reinterpret_cast<const v4f*>(src + 4 * r4);
                 } else {
-                    v4f v = {0.f, 0.f, 0.f, 0.f};
-                    if (kl + s < w)
-                        for (int e = 0; e < 4; ++e)
-                            if (rl + e < a.m) v[e] = p[e];
-                    x[s] = v;
+                    for (int e = 0; e < 4; ++e)
+                        if (4 * r4 + e < a.m) v[e] = src[4 * r4 + e];
                 }
+                xa[t] = v;
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < kOPieces; ++t) {
+            const int it = tg + t * kGenThreads;
+            constexpr int PPC = BN * kKC / 4;                   // pieces per chunk
+            const int ci = it / PPC;
+            const int pc = it - ci * PPC;
+            const int c = min(gi * kSkG + ci, nchunks - 1);
+            const int n = pc / (kKC / 4);
+            const int kl4 = (pc - n * (kKC / 4)) * 4;
+            xo[t] = *reinterpret_cast<const v4f*>(
+                a.fpack + (((int64_t)strip * (kMfmaStrip / kKC) + c) * a.kpad + n_base + n) * kKC + kl4);
+        }
+    };
+    auto g_store = [&](int gi, const v4f* xa, const v4f* xo) {
+        const int slot0 = (gi & 1) * kSkG;
+#pragma unroll
+        for (int t = 0; t < kAPieces; ++t) {
+            const int p = tg + t * kGenThreads;
+            const int ci = p / (kKC * 16);
+            const int rem = p - ci * (kKC * 16);
+            const int col = rem >> 4;
+            const int r4 = rem & 15;
+            const bool inside = (gi * kSkG + ci) * kKC + col < w;
+            float* dst = &as[slot0 + ci][col][r4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) dst[16 * e] = inside ? xa[t][e] : 0.0f;
+        }
+#pragma unroll
+        for (int t = 0; t < kOPieces; ++t) {
+            const int it = tg + t * kGenThreads;
+            constexpr int PPC = BN * kKC / 4;
+            const int ci = it / PPC;
+            const int pc = it - ci * PPC;
+            const int n = pc / (kKC / 4);
+            const int kl4 = (pc - n * (kKC / 4)) * 4;
+            *reinterpret_cast<v4f*>(&om[slot0 + ci][n][kl4]) = xo[t];
+        }
+    };
+
+    v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
+    auto chain_group = [&](int gi) {
+        const int slot0 = (gi & 1) * kSkG;
+#pragma unroll
+        for (int cc = 0; cc < kSkG; ++cc) {
+            if (gi * kSkG + cc < nchunks) {
+                const float* ob = &om[slot0 + cc][j][4 * kLV * g];
+                v4f wop[kLV];
+#pragma unroll
+                for (int v = 0; v < kLV; ++v) wop[v] = *reinterpret_cast<const v4f*>(ob + 4 * v);
+                const float* ab = &as[slot0 + cc][g * kNS][16 * q + j];
+                float x[kNS];
+#pragma unroll
+                for (int s = 0; s < kNS; ++s) x[s] = ab[s * kAP];
+#pragma unroll
+                for (int v = 0; v < kLV; ++v)
+#pragma unroll
+                    for (int s = 0; s < 4; ++s)
+                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wop[v][s], x[4 * v + s], acc, 0, 0, 0);
             }
         }
     };
 
-    // A chunks in a ring of kDepth register buffers (chain waves only)
-    constexpr int kDepth = 4;
-    static_assert(kSkG % kDepth == 0, "ring steps per group");
-    v4f ab[kDepth][kNS];
-    v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
-    if (!gen_wave) {
-#pragma unroll
-        for (int d = 0; d < kDepth - 1; ++d) load_a(ab[d], d);
-    } else {
-        gen_group(0);
+    v4f ra[kAPieces], ro[kOPieces], rb[kAPieces], rbo[kOPieces];
+    if (gen_wave) {
+        g_load(0, ra, ro);
+        g_store(0, ra, ro);
+        g_load(min(1, ngroups - 1), ra, ro);
     }
     lds_barrier_m();
-    for (int gi = 0; gi < ngroups; ++gi) {
+    // group gi: the chains use slot gi & 1; the stagers store group gi + 1 (held in
+    // cur) into the other slot after issuing the loads of group gi + 2 into nxt
+    auto iter = [&](int gi, v4f* cur_a, v4f* cur_o, v4f* nxt_a, v4f* nxt_o) {
         if (gen_wave) {
-            if (gi + 1 < ngroups) gen_group(gi + 1);
+            g_load(min(gi + 2, ngroups - 1), nxt_a, nxt_o);
+            if (gi + 1 < ngroups) g_store(gi + 1, cur_a, cur_o);
         } else {
-            for (int c0 = gi * kSkG; c0 < (gi + 1) * kSkG; c0 += kDepth) {
-#pragma unroll
-                for (int d = 0; d < kDepth; ++d) {
-                    const int c = c0 + d;
-                    if (c < nchunks) {
-                        const float* ob = &om[(gi & 1) * kSkG + (c - gi * kSkG)][j][4 * kLV * g];
-                        v4f wop[kLV];
-#pragma unroll
-                        for (int v = 0; v < kLV; ++v) wop[v] = *reinterpret_cast<const v4f*>(ob + 4 * v);
-                        if (ALIGNED && (c + 1) * kKC > w) {      // the strip's partial last chunk
-                            const int kl = c * kKC + g * kNS;
-#pragma unroll
-                            for (int s = 0; s < kNS; ++s)
-                                if (kl + s >= w) ab[d][s] = v4f{0.f, 0.f, 0.f, 0.f};
-                        }
-#pragma unroll
-                        for (int v = 0; v < kLV; ++v)
-#pragma unroll
-                            for (int s = 0; s < 4; ++s)
-                                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wop[v][s], ab[d][4 * v + s][q],
-                                                                           acc, 0, 0, 0);
-                        if constexpr (!ALIGNED) load_a(ab[(d + kDepth - 1) % kDepth], c + kDepth - 1);
-                    }
-                    if constexpr (ALIGNED) {
-                        // every step issues its loads (the compiler then waits for one buffer)
-                        load_a(ab[(d + kDepth - 1) % kDepth], c + kDepth - 1);
-                        __builtin_amdgcn_sched_barrier(0);
-                    }
-                }
-            }
+            chain_group(gi);
         }
         lds_barrier_m();
+    };
+    for (int gi = 0; gi < ngroups; gi += 2) {
+        iter(gi, ra, ro, rb, rbo);
+        if (gi + 1 < ngroups) iter(gi + 1, rb, rbo, ra, ro);
     }
     if (gen_wave) return;
 
