@@ -965,7 +965,8 @@ __global__ __launch_bounds__(kThreads) void k_gemm_cm_mfma(const CmMArgs a) {
 // bit; waves 4..7 stage kSkG chunks at a time, A and the call's packed Omega,
 // into the other half of a double-buffered LDS ring, with the loads of the group
 // after next in flight while they store the next one.  A chain's step then waits
-// on LDS only, not on a global load.
+// on LDS only, not on a global load.  The launch always packs the call's Omega
+// for this kernel (a.fpack is set).
 constexpr int kSkG = 4;
 
 template <int kKC, bool ALIGNED>
