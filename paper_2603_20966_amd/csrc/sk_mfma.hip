@@ -962,19 +962,23 @@ __global__ __launch_bounds__(kThreads) void k_gemm_cm_mfma(const CmMArgs a) {
 // 16 sketch columns, and its waves split the work: waves 0..3 each run one chain
 // (row set q = wave: rows 4j + q of lane j) with the steps, operands and order of
 // the kernel above, so the results equal it (and the row-major kernel) bit for
-// bit; waves 4..7 stage kSkG chunks at a time, A and the call's packed Omega,
+// bit; waves 4..11 stage kSkG chunks at a time, A and the call's packed Omega,
 // into the other half of a double-buffered LDS ring, with the loads of the group
 // after next in flight while they store the next one.  A chain's step then waits
 // on LDS only, not on a global load.  The launch always packs the call's Omega
-// for this kernel (a.fpack is set).
+// for this kernel (a.fpack is set).  Eight staging waves rather than four: the
+// staging alone took most of the kernel's time.
 constexpr int kSkG = 4;
+constexpr int kSkChainThreads = 256;                       // waves 0..3
+constexpr int kSkGenThreads = 512;                         // waves 4..11
+constexpr int kSkThreads = kSkChainThreads + kSkGenThreads;
 
 template <int kKC, bool ALIGNED>
-__global__ __launch_bounds__(kThreads) void k_gemm_cm_mfma_skinny(const CmMArgs a) {
+__global__ __launch_bounds__(kSkThreads) void k_gemm_cm_mfma_skinny(const CmMArgs a) {
     constexpr int BN = 16;
     constexpr int kNS = kKC / 4;
     constexpr int kLV = kKC / 16;
-    constexpr int kGenThreads = kThreads / 2;
+    constexpr int kGenThreads = kSkGenThreads;
     // a staged column of A: row 4j + q at [q][j], 2 floats of padding so that the
     // four lane groups of a chain's read (8 columns apart) fall on different banks
     constexpr int kAP = 66;
@@ -1005,7 +1009,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm_cm_mfma_skinny(const CmMArgs 
     const int64_t rl = 4 * j;                               // first row of the lane
 
     // columns past k of every slot are zero (the packed plane holds zeros there too)
-    for (int it = threadIdx.x; it < 2 * kSkG * BN * (kKC + 4); it += kThreads) {
+    for (int it = threadIdx.x; it < 2 * kSkG * BN * (kKC + 4); it += kSkThreads) {
         const int n = (it / (kKC + 4)) % BN;
         if (n >= kb) (&om[0][0][0])[it] = 0.0f;
     }
@@ -1015,7 +1019,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm_cm_mfma_skinny(const CmMArgs 
     // columns past the strip's end read its last column), so the compiler waits for
     // the older group only; columns past the strip's end are stored as zeros, rows
     // past m are never stored by the chains.
-    const int tg = threadIdx.x - kGenThreads;
+    const int tg = threadIdx.x - kSkChainThreads;
     auto g_load = [&](int gi, v4f* xa, v4f* xo) {
 #pragma unroll
         for (int t = 0; t < kAPieces; ++t) {
@@ -1907,10 +1911,10 @@ hipError_t launch_gemm_cm_mfma(const CmLaunch& g) {
     if (skinny) {
         if (g.m % 4 == 0)
             hipLaunchKernelGGL((k_gemm_cm_mfma_skinny<KC, true>), dim3((unsigned)a.tiles),
-                               dim3(kThreads), 0, g.stream, a);
+                               dim3(kSkThreads), 0, g.stream, a);
         else
             hipLaunchKernelGGL((k_gemm_cm_mfma_skinny<KC, false>), dim3((unsigned)a.tiles),
-                               dim3(kThreads), 0, g.stream, a);
+                               dim3(kSkThreads), 0, g.stream, a);
         e = hipGetLastError();
     } else switch (nt) {
     case 1: e = launch_cm_mfma_nt<1, KC>(a, g.stream); break;
