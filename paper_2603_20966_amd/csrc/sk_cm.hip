@@ -198,9 +198,10 @@ __global__ __launch_bounds__(256) void k_gemm_cm(const CmArgs a) {
 // narrow sketch): the tile above would leave all but m/4 lanes of one wave
 // idle and walk each wave's 256 columns of a strip one load round at a time.
 // Here a workgroup takes one strip and one group of sketch columns; all its
-// kSkinnyThreads threads stage the strip's columns of A (all 1024 at once for m <= 8 and
-// k <= 8, else 256 at a time) and their Omega rows in LDS, and thread (w, i, c) runs the chain that wave w of the tile kernel
-// runs for row i and sketch column c (waves 0..3): columns j = w, w + 4, ... of
+// kSkinnyThreads threads stage the strip's 1024 columns of A (room for 8 rows when
+// m <= 8 and k <= 8, else 16) and their Omega rows in LDS at once, and thread
+// (w, i, c) runs the chain that wave w of the tile kernel runs for row i and
+// sketch column c (waves 0..3): columns j = w, w + 4, ... of
 // the strip in order, FP32 fma, then the four chains added in wave order.  Every
 // sum is the tile kernel's, bit for bit.  The other twelve waves only help stage:
 // with four waves the Philox work of a strip (1280 quads at k = 5) ran five quads
@@ -350,8 +351,8 @@ hipError_t launch_cm_k(const CmArgs& a, hipStream_t s) {
                 return hipGetLastError();
             }
         }
-        hipLaunchKernelGGL((k_gemm_cm_skinny<K, 256, kSkinnyRows>), grid, dim3(kSkinnyThreads), 0, s,
-                           a);
+        hipLaunchKernelGGL((k_gemm_cm_skinny<K, cm_strip_width(K), kSkinnyRows>), grid,
+                           dim3(kSkinnyThreads), 0, s, a);
         return hipGetLastError();
     }
     hipLaunchKernelGGL((k_gemm_cm<K>), dim3((unsigned)(8 * a.tiles8)), dim3(256), 0, s, a);
